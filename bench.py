@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Decomposed Mpixel/s of the alternating Gauss-Newton decomposition on one MI355X.
+
+A step decomposes one whole synthetic clip: every frame goes through the fixed
+schedule (G outer iterations of a layer step with P PCG iterations and a
+base-colour step), warm-started from the previous frame with the temporal
+prior on, starting from the initial colour estimate.  Inputs are resident in
+device memory before timing starts; per-frame layers are written to device
+memory.  Default workload: 640x480, 30 frames, K = 6, G x P = 3 x 8.
+
+Prints one JSON line.  Besides the throughput it reports the roofline of the
+dominant kernel (the matrix-free J^T J matvec, timed with HIP events on the
+solver's stream in a profiled pass over the same clip) and the FP64 oracle
+timed on host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(n: int, tau: int, G: int, P: int) -> dict:
+    """Bytes per pixel the method must move with FP32 state and the operator
+    recomputed from the unknowns (q kept on chip in a fused PCG iteration)."""
+    return dict(pcg_iter=4 * (7 * n + 1 + tau),
+                matvec=4 * (3 * n + 1 + tau),     # read p, u, w_SR, pair count; write q
+                frame=4 * G * (P * (7 * n + 1 + tau) + 7 * n + 7 + 3 * tau))
+
+
+def cpu_baseline(clip, G, P, frames):
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.decompose_clip(clip.frames, clip.ids, clip.b_init, O.default_params(), G, P, temporal=True,
+                         nframes=frames)
+        dt = time.perf_counter() - t0
+    px = frames * clip.width * clip.height
+    return dict(value=px / dt / 1e6, unit="Mpx/s", cores=1, kind="oracle",
+                sample=f"first {frames} frame(s) of the {clip.width}x{clip.height} K={clip.K} clip, "
+                       f"same {G}x{P} schedule, FP64 NumPy, 1 thread; {dt:.1f} s",
+                host_cpus=os.cpu_count(), host_affinity=len(os.sched_getaffinity(0)))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="video_640x480_k6")
+    ap.add_argument("--frames", type=int, default=None, help="frames per clip (default: the workload's)")
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of graph replay")
+    ap.add_argument("--cpu-frames", type=int, default=3, help="oracle sample size in frames (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver is single-GPU (clips would shard across GPUs with "
+              "no communication); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1908_01961_amd as G
+    from scenes import WORKLOADS, workload_clip
+
+    w = WORKLOADS[args.workload]
+    F = args.frames or w["frames"]
+    print(f"[bench] generating {args.workload} ({F} frames)", file=sys.stderr, flush=True)
+    clip = workload_clip(args.workload, nframes=F)
+    W_, H_, K = clip.width, clip.height, clip.K
+    n = K + 4
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    frames = torch.from_numpy(clip.frames).to(dev)
+    ids = torch.from_numpy(clip.ids).to(dev)
+    layers = torch.empty((F, n, H_, W_), dtype=torch.float32, device=dev)
+    prm = G.default_params(K, gn_iters=w["G"], pcg_iters=w["P"], temporal=int(w["temporal"]),
+                           refine_mode="every", record_energy=0, use_graph=0 if args.no_graph else 1)
+    solver = G.Solver(W_, H_, prm)
+
+    def step():
+        solver.set_base_colors(clip.b_init)
+        for t in range(F):
+            solver.decompose_frame_async(frames[t], ids[t], layers[t])
+        return solver.synchronize()
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    last = None
+    for _ in range(args.steps):
+        last = step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = wall * 1e3 / args.steps
+    px = F * W_ * H_
+    value = px * args.steps / wall / 1e6
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} Mpx/s", file=sys.stderr,
+          flush=True)
+    b_final, stats = last
+
+    # profiled pass: per-kernel durations from HIP events on the solver's stream
+    solver.set_profiling(True)
+    step()
+    kt = solver.kernel_times()
+    solver.set_profiling(False)
+    mv = kt["matvec"]
+    mv_avg_s = mv["ms"] / max(1, mv["launches"]) / 1e3
+    tau = 1 if w["temporal"] else 0
+    ab = algorithmic_bytes(n, tau, w["G"], w["P"])
+    mv_bytes = ab["matvec"] * W_ * H_
+    achieved = mv_bytes / mv_avg_s / 1e9
+    frame_ms = ms_per_step / F
+    frame_gbs = ab["frame"] * W_ * H_ / (frame_ms / 1e3) / 1e9
+    roofline = dict(bound="hbm", kernel="k_matvec", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    algorithmic_bytes_per_launch=mv_bytes, avg_launch_us=round(mv_avg_s * 1e6, 2))
+    kernels = {k: dict(avg_us=round(v["ms"] * 1e3 / v["launches"], 2), launches=v["launches"],
+                       share=round(v["ms"] / max(1e-12, sum(x["ms"] for x in kt.values())), 4))
+               for k, v in kt.items() if v["launches"]}
+
+    cpu = None
+    if args.cpu_frames > 0:
+        print(f"[bench] oracle on {args.cpu_frames} frame(s)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(clip, w["G"], w["P"], min(args.cpu_frames, F))
+
+    out = {
+        "metric": "decomposed Mpixel/s at fixed final energy (1 GPU); learned warm-start vs plain",
+        "value": round(value, 2),
+        "unit": "Mpx/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 reductions)",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "width": W_, "height": H_, "frames": F, "K": K,
+                   "gn_iters": w["G"], "pcg_iters": w["P"], "temporal": bool(w["temporal"]),
+                   "refine": "every", "method": "plain", "graph": not args.no_graph},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "frame_roofline": dict(achieved=round(frame_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=round(frame_gbs / HBM_PEAK_GBS, 4),
+                               algorithmic_bytes_per_frame=ab["frame"] * W_ * H_),
+        "gpu_event_ms_per_step": round(gpu_ms / args.steps, 3),
+        "final_energy_last_frame": stats["energy_final"],
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+    solver.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,209 @@
+/*
+ * gid.h -- C ABI of libgid, an MI355X (gfx950) solver for the global-illumination
+ * decomposition of videos of Meka et al., "Real-Time Global Illumination
+ * Decomposition of Videos".
+ *
+ * Problem (Sec. 3, eq. imageformation): every RGB frame I is factored as
+ *     I(x) = R(x) * sum_{k=0..K} b_k T_k(x),   b_0 = (1,1,1),
+ * into a reflectance layer R, a direct-illumination layer T_0, one indirect layer
+ * T_k per base colour b_k, and K refined base colours.  The solver minimises the
+ * energy of Sec. 5 (data + reflectance priors + illumination priors, l1 terms by
+ * IRLS, Sec. 5.4) with the alternating scheme of Sec. 6.1: a Gauss-Newton step on
+ * the per-pixel layers whose normal equations get a fixed number of Jacobi-PCG
+ * iterations, then a Gauss-Newton step on the base colours whose 3K x 3K normal
+ * equations are summed over all pixels.
+ *
+ * Conventions shared by every call
+ *  - Every call returns gid_status; nothing throws across the ABI.
+ *  - Device pointers are HIP device memory of the device current at gid_create.
+ *    The caller owns every buffer it passes; the library owns its workspace,
+ *    allocated by gid_create from (width, height, K) and freed by gid_destroy.
+ *    Solve calls allocate nothing.
+ *  - Layout: planes of width*height float32 in row-major order (row pitch =
+ *    width), planes back to back.  A frame is 3 planes (R, G, B; linear RGB).
+ *    Layers are K+4 planes: log-reflectance is optimised internally, the output
+ *    planes are R_r, R_g, R_b (linear reflectance), T_0, T_1 .. T_K.
+ *    Cluster ids are width*height uint8 in [0, K): id j names base colour b_{j+1}.
+ *  - Work is enqueued on the HIP stream given at gid_create, in stream order.
+ *    Host outputs of a solve (base colours, statistics) are valid after
+ *    gid_synchronize.
+ *  - On an argument error nothing is enqueued and the context is unchanged.
+ *  - One context per host thread; a context is bound to one device.
+ */
+#ifndef GID_H
+#define GID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gid_ctx gid_ctx;
+
+typedef enum {
+    GID_OK = 0,
+    GID_ERR_INVALID_ARG = 1,
+    GID_ERR_OUT_OF_MEMORY = 2,
+    GID_ERR_HIP = 3,
+    GID_ERR_NUMERIC = 4,      /* non-finite energy or input */
+    GID_ERR_STATE = 5,        /* call out of order (e.g. no frame loaded) */
+    GID_ERR_UNSUPPORTED = 6
+} gid_status;
+
+/* Energy weights of Sec. 7 ("Parameters"): data 5000, clustering 200,
+ * reflectance sparsity 20 with exponent p = 1, consistency 10, monochromaticity 10,
+ * indirect sparsity 3, smoothness 3, non-negativity 1000, base-colour intensity
+ * regulariser 10 and chromaticity regulariser 100. */
+typedef struct {
+    float data, cluster, r_sparsity, p, r_consistency, monochrome,
+          i_sparsity, smoothness, non_neg, ir, cr;
+} gid_lambdas;
+
+enum { GID_REFINE_OFF = 0, GID_REFINE_FIRST_FRAME = 1, GID_REFINE_EVERY_STEP = 2 };
+enum { GID_CR_CHROMA = 0, GID_CR_LITERAL = 1 };
+
+typedef struct {
+    uint32_t struct_size;      /* sizeof(gid_params), set by gid_default_params */
+    int32_t K;                 /* number of base colours, 1..16 */
+    gid_lambdas lambda;
+    float eps_nonneg;          /* 0.002, non-negativity reweighting (Sec. 5.4.1) */
+    float eps_irls;            /* 0.002, guard of the l1/l_p IRLS weights */
+    float retinex_k;           /* 50, soft-Retinex weight 1 - exp(-50 dC) (Sec. 5.2) */
+    double chroma_gate;        /* 0.1, temporal pair gate on |C_t(x) - C_{t-1}(y)|_2 */
+    double chroma_floor;       /* 1e-6, chromaticity is white below this intensity */
+    int32_t gn_iters;          /* outer iterations per frame (G) */
+    int32_t pcg_iters;         /* PCG iterations per layer step (P); the paper uses 16 */
+    int32_t refine_mode;       /* GID_REFINE_*; default every step */
+    int32_t temporal;          /* 1: consistency prior against the previous frame */
+    int32_t cr_mode;           /* GID_CR_* */
+    int32_t record_energy;     /* 1: evaluate E after every half-step (extra passes) */
+    int32_t use_graph;         /* 1: replay the per-frame schedule as a hipGraph */
+} gid_params;
+
+#define GID_MAX_HALF_STEPS 128
+#define GID_NUM_TERMS 8        /* data, cluster, rsparsity, rconsist, mono, isparsity, smooth, nonneg */
+
+typedef struct {
+    double energy_final;                        /* E of Sec. 5 at the frame's final state, FP64 */
+    double energy_terms[GID_NUM_TERMS];         /* its terms */
+    double energy_half[GID_MAX_HALF_STEPS];     /* E after each half-step (record_energy) */
+    double pcg_rz_last[64];                     /* <r, z> after the last PCG iteration of each GN step */
+    int32_t n_half;                             /* entries of energy_half */
+    int32_t gn_done;                            /* outer iterations run */
+    int32_t pcg_breakdowns;                     /* PCG stopped early by a breakdown guard */
+    int32_t bstep_rejected;                     /* base-colour steps rejected by a guard */
+    int32_t frame_index;                        /* 0 for the first frame of the clip */
+} gid_frame_stats;
+
+/* Fill *out with the paper's parameters for K base colours (Sec. 7) and the
+ * schedule defaults G = 3, P = 8, refinement every step, temporal prior on.
+ * Errors: GID_ERR_INVALID_ARG for K outside 1..16 or out == NULL. */
+gid_status gid_default_params(int32_t K, gid_params *out);
+
+/* Create a solver context for frames of width x height (each >= 2) and K base
+ * colours, enqueuing on hip_stream (a hipStream_t; NULL = the null stream).
+ * Allocates the whole workspace.  Errors: GID_ERR_INVALID_ARG (bad params or
+ * size), GID_ERR_OUT_OF_MEMORY, GID_ERR_HIP. */
+gid_status gid_create(const gid_params *params, int32_t width, int32_t height,
+                      void *hip_stream, gid_ctx **out);
+
+/* Free the context and its workspace (waits for its stream first). NULL is a no-op. */
+gid_status gid_destroy(gid_ctx *ctx);
+
+/* Set the initial base-colour estimate b_k^init (K x 3 linear RGB, host memory,
+ * FP64, every component > 0) and start a new clip: the next solve is a first frame
+ * (Sec. 4.1 initialisation, no temporal prior).  Errors: GID_ERR_INVALID_ARG. */
+gid_status gid_set_base_colors(gid_ctx *ctx, const double *rgb_Kx3_host);
+
+/* Start a new clip with the current initial colours (as after gid_set_base_colors). */
+gid_status gid_reset_clip(gid_ctx *ctx);
+
+/* Decompose one frame (Sec. 6.1 schedule).
+ *   frame_dev       3 planes float32 (device), read during the call's stream work
+ *   cluster_ids_dev width*height uint8 (device), values in [0, K)
+ *   layers_dev      K+4 planes float32 (device) written: R_r, R_g, R_b, T_0..T_K; may be NULL
+ *   base_colors_host K x 3 double written after gid_synchronize; may be NULL
+ *   stats           filled after gid_synchronize; may be NULL
+ * The first frame of a clip starts from r = ln b_id, T_0 = clip(|I|/|R|, 0, 4),
+ * T_k = 0.01; later frames start from the previous frame's result and, with
+ * params.temporal, add the consistency prior against it.
+ * Errors: GID_ERR_INVALID_ARG (NULL frame or ids), GID_ERR_STATE (no base
+ * colours set), GID_ERR_HIP. */
+gid_status gid_decompose_frame(gid_ctx *ctx, const float *frame_dev, const uint8_t *cluster_ids_dev,
+                               float *layers_dev, double *base_colors_host, gid_frame_stats *stats);
+
+/* Wait for the context's stream; completes pending host outputs.  Returns
+ * GID_ERR_NUMERIC if the last frame's final energy is not finite. */
+gid_status gid_synchronize(gid_ctx *ctx);
+
+/* ---- single-step access (each step of the schedule on the current frame) ----
+ * These run one step of the hot path on the frame loaded by gid_load_frame and
+ * the state set by gid_set_state, so that each step can be checked on its own. */
+
+/* Load a frame without solving: per-frame precompute (chromaticity, soft-Retinex
+ * weight Sec. 5.2, temporal pairs against the previous frame when params.temporal
+ * and a previous frame exists).  Initialises the state for a first frame. */
+gid_status gid_load_frame(gid_ctx *ctx, const float *frame_dev, const uint8_t *cluster_ids_dev);
+
+/* Overwrite the unknowns: u_dev = K+4 planes (r_0, r_1, r_2 = ln R, T_0..T_K,
+ * device) and b (K x 3 doubles, host, may be NULL to keep the current colours). */
+gid_status gid_set_state(gid_ctx *ctx, const float *u_dev, const double *b_host);
+
+/* Copy out the unknowns (same layout as gid_set_state); b_host may be NULL.
+ * Synchronous. */
+gid_status gid_get_state(gid_ctx *ctx, float *u_dev, double *b_host);
+
+/* E of Sec. 5 and its GID_NUM_TERMS terms at the current state, FP64. Synchronous. */
+gid_status gid_eval_energy(gid_ctx *ctx, double *energy_out, double *terms_out);
+
+/* Gauss-Newton right-hand side g = -J^T F and Jacobi diagonal diag(J^T J) of the
+ * IRLS surrogate linearised at the current state (K+4 planes each, device). */
+gid_status gid_eval_rhs(gid_ctx *ctx, float *g_dev, float *diag_dev);
+
+/* q = J^T J p for the surrogate linearised at the current state (device planes). */
+gid_status gid_apply_normal(gid_ctx *ctx, const float *p_dev, float *q_dev);
+
+/* One layer step: PCG on the normal equations, then u += delta.  *rz_out (host,
+ * may be NULL) gets the final <r, z>.  Synchronous. */
+gid_status gid_layer_step(gid_ctx *ctx, double *rz_out);
+
+/* Base-colour step sums at the current state (Sec. 6.1): A[c][k][l] =
+ * lam_d sum_x R_c^2 T_k T_l and h[c][k] = lam_d sum_x R_c T_k (I_c - R_c S_c),
+ * FP64, host arrays of 3*K*K and 3*K doubles.  Synchronous. */
+gid_status gid_bstep_sums(gid_ctx *ctx, double *A_host, double *h_host);
+
+/* One base-colour step (sums + small FP64 solve + update).  *accepted (host,
+ * may be NULL) is 0 when a guard rejected the step.  Synchronous. */
+gid_status gid_base_step(gid_ctx *ctx, int32_t *accepted);
+
+/* ---- kernel timing ----
+ * With profiling on, the following solves launch kernels directly (no graph)
+ * with a HIP event pair around every launch on the context's stream; the
+ * elapsed times are accumulated per kernel kind at gid_synchronize. */
+enum {
+    GID_KERNEL_SCAN = 0, GID_KERNEL_PRECOMPUTE, GID_KERNEL_GN_BUILD, GID_KERNEL_MATVEC,
+    GID_KERNEL_UPDATE, GID_KERNEL_APPLY_BSUM, GID_KERNEL_BSOLVE, GID_KERNEL_ENERGY,
+    GID_KERNEL_OUTPUT, GID_NUM_KERNEL_KINDS
+};
+/* Turn profiling on (1) or off (0); turning it on clears the accumulated times. */
+gid_status gid_set_profiling(gid_ctx *ctx, int32_t enable);
+/* Accumulated milliseconds and launch counts per kernel kind (arrays of
+ * GID_NUM_KERNEL_KINDS entries, host). */
+gid_status gid_get_kernel_times(gid_ctx *ctx, double *ms_out, int64_t *launches_out);
+
+/* ---- checkpoint / resume ---- */
+/* Serialise the solver state (unknowns, colours, previous-frame data, frame
+ * index).  With buf == NULL, *inout_bytes receives the required size. Synchronous. */
+gid_status gid_save_state(gid_ctx *ctx, void *buf, size_t *inout_bytes);
+gid_status gid_load_state(gid_ctx *ctx, const void *buf, size_t bytes);
+
+const char *gid_status_string(gid_status s);
+/* Last error message of this context (valid until its next call). */
+const char *gid_last_error(const gid_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GID_H */

@@ -1,0 +1,847 @@
+// libgid host runtime: context and workspace, the per-frame schedule of the
+// alternating solve (Sec. 6.1), hipGraph replay of that schedule, single-step
+// access, checkpoint/resume, and the C ABI declared in gid.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "gid_internal.h"
+
+using namespace gid;
+
+namespace {
+
+constexpr int FINAL_SLOT = ELOG_SLOTS - 2;   // energy of the frame when half-steps are not recorded
+constexpr int PROBE_SLOT = ELOG_SLOTS - 1;   // single-step energy evaluation
+constexpr int NB_MAX = 1024;                 // workgroups of a per-pixel launch (partials per reduction)
+constexpr int NB_BS_MAX = 512;               // workgroups of the apply + base-colour-sum pass
+constexpr uint32_t STATE_MAGIC = 0x67696431u; // "gid1"
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct gid_ctx {
+    gid_params prm{};
+    int W = 0, H = 0, K = 0, n = 0;
+    long long ps = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void* arena = nullptr;
+    // device workspace
+    float *u = nullptr, *delta = nullptr, *res = nullptr, *pA = nullptr, *pB = nullptr, *q = nullptr,
+          *minv = nullptr, *I = nullptr, *wsr = nullptr, *tg = nullptr, *Iprev = nullptr,
+          *rprev = nullptr, *bf = nullptr, *lnb = nullptr;
+    uint8_t* ids = nullptr;
+    double *b64 = nullptr, *lnb64 = nullptr, *binit64 = nullptr, *scal = nullptr, *partials = nullptr,
+           *elog = nullptr, *bsum = nullptr;
+    unsigned* tickets = nullptr;
+    long long part_stride = 0;
+    // pinned host mirrors
+    double* h_scal = nullptr;
+    double* h_elog = nullptr;
+    double* h_b64 = nullptr;
+    double* h_small = nullptr;     // staging for host -> device colour uploads
+    // tiling
+    int ppt = 1, ntx = 0, nty = 0, ntiles = 0, nblocks = 0, nb_bs = 0;
+    // clip state
+    bool colors_set = false, have_prev = false;
+    int frame_index = 0;
+    double binit_host[3 * KMAX] = {};
+    // pending host outputs of the last frame
+    bool pending = false;
+    double* pend_b = nullptr;
+    gid_frame_stats* pend_stats = nullptr;
+    int pend_nhalf = 0, pend_final_slot = FINAL_SLOT, pend_frame = 0, pend_gn = 0;
+    bool pend_had_prev = false;
+    // replayable schedules keyed by (refine, temporal, record)
+    hipGraphExec_t graphs[8] = {};
+    hipStream_t cap_stream = nullptr;
+    // kernel timing
+    bool profiling = false;
+    static constexpr int NEV = 8192;
+    hipEvent_t ev[NEV] = {};
+    int ev_kind[NEV / 2] = {};
+    int ev_used = 0;
+    double kind_ms[GID_NUM_KERNEL_KINDS] = {};
+    int64_t kind_n[GID_NUM_KERNEL_KINDS] = {};
+    std::string err;
+};
+
+namespace {
+
+gid_status fail(gid_ctx* c, gid_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define GID_HIP(c, call)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail((c), GID_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Launch through fn; with profiling on, bracket the launch with an event pair.
+template <typename Fn>
+hipError_t timed(gid_ctx* c, int kind, Fn&& fn) {
+    if (!c->profiling || c->ev_used + 2 > gid_ctx::NEV) return fn();
+    hipEvent_t& e0 = c->ev[c->ev_used];
+    hipEvent_t& e1 = c->ev[c->ev_used + 1];
+    hipError_t e;
+    if (!e0 && (e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if (!e1 && (e = hipEventCreate(&e1)) != hipSuccess) return e;
+    if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) return e;
+    if ((e = fn()) != hipSuccess) return e;
+    if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) return e;
+    c->ev_kind[c->ev_used / 2] = kind;
+    c->ev_used += 2;
+    return hipSuccess;
+}
+
+// Accumulate the recorded event pairs (the stream must be idle).
+hipError_t collect_times(gid_ctx* c) {
+    for (int i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
+        if (e != hipSuccess) return e;
+        c->kind_ms[c->ev_kind[i / 2]] += ms;
+        c->kind_n[c->ev_kind[i / 2]] += 1;
+    }
+    c->ev_used = 0;
+    return hipSuccess;
+}
+
+#define GID_T(KIND, CALL) timed(c, KIND, [&]() { return (CALL); })
+
+Lam make_lam(const gid_params& p) {
+    Lam L;
+    L.data = p.lambda.data;
+    L.cl = p.lambda.cluster;
+    L.rs = p.lambda.r_sparsity;
+    L.p = p.lambda.p;
+    L.rc = p.lambda.r_consistency;
+    L.mo = p.lambda.monochrome;
+    L.is = p.lambda.i_sparsity;
+    L.sm = p.lambda.smoothness;
+    L.nn = p.lambda.non_neg;
+    L.ir = p.lambda.ir;
+    L.cr = p.lambda.cr;
+    L.eps_nn = p.eps_nonneg;
+    L.eps_irls = p.eps_irls;
+    L.rk = p.retinex_k;
+    L.gate = p.chroma_gate;
+    L.cfloor = p.chroma_floor;
+    return L;
+}
+
+Args base_args(const gid_ctx* c) {
+    Args a;
+    std::memset(&a, 0, sizeof(a));
+    a.W = c->W;
+    a.H = c->H;
+    a.K = c->K;
+    a.ppt = c->ppt;
+    a.ntx = c->ntx;
+    a.nty = c->nty;
+    a.ntiles = c->ntiles;
+    a.nblocks = c->nblocks;
+    a.ps = c->ps;
+    a.lam = make_lam(c->prm);
+    a.cr_literal = c->prm.cr_mode == GID_CR_LITERAL;
+    a.add_delta = 1;
+    a.u = c->u;
+    a.delta = c->delta;
+    a.res = c->res;
+    a.pold = c->pA;
+    a.pnew = c->pA;
+    a.q = c->q;
+    a.minv = c->minv;
+    a.I = c->I;
+    a.ids = c->ids;
+    a.wsr = c->wsr;
+    a.tg = c->tg;
+    a.Iprev = c->Iprev;
+    a.rprev = c->rprev;
+    a.bf = c->bf;
+    a.lnb = c->lnb;
+    a.b64 = c->b64;
+    a.lnb64 = c->lnb64;
+    a.binit64 = c->binit64;
+    a.scal = c->scal;
+    a.partials = c->partials;
+    a.tickets = c->tickets;
+    a.elog = c->elog;
+    a.bsum = c->bsum;
+    a.part_stride = c->part_stride;
+    return a;
+}
+
+// Tile height: the smallest rows-per-thread that keeps the grid near 4096
+// workgroups (enough to fill 256 CUs several times, few enough partials).
+int choose_ppt(int W, int H) {
+    const int ntx = (W + TX - 1) / TX;
+    for (int ppt : {1, 2, 4, 8}) {
+        const int nty = (H + TYW * ppt - 1) / (TYW * ppt);
+        if ((long long)ntx * nty <= 4096) return ppt;
+    }
+    return 8;
+}
+
+// Each workgroup of a per-pixel launch owns a contiguous chunk of tiles; the
+// chunks are balanced (every workgroup gets the same number of tiles up to one)
+// and the workgroup count is a multiple of 8 for the XCD-aware order.
+void set_tiling(gid_ctx* c, int ppt) {
+    c->ppt = ppt;
+    c->ntx = (c->W + TX - 1) / TX;
+    c->nty = (c->H + TYW * ppt - 1) / (TYW * ppt);
+    c->ntiles = c->ntx * c->nty;
+    const int per = (c->ntiles + NB_MAX - 1) / NB_MAX;
+    const int nb = (c->ntiles + per - 1) / per;
+    c->nblocks = (int)align_up((size_t)nb, 8);
+    c->nb_bs = std::min(c->nblocks, NB_BS_MAX);
+}
+
+// Upload colours b (K x 3 doubles) into b64 / bf / lnb / lnb64 (and the initial
+// estimate when init is true) through the pinned staging buffer.
+gid_status upload_colours(gid_ctx* c, const double* b, bool init) {
+    const int nk = 3 * c->K;
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    double* st = c->h_small;
+    float* stf = reinterpret_cast<float*>(st + 4 * 3 * KMAX);
+    for (int i = 0; i < nk; ++i) {
+        st[i] = b[i];
+        st[3 * KMAX + i] = std::log(b[i]);
+        stf[i] = (float)b[i];
+        stf[3 * KMAX + i] = (float)std::log(b[i]);
+    }
+    GID_HIP(c, hipMemcpyAsync(c->b64, st, nk * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->lnb64, st + 3 * KMAX, nk * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->bf, stf, nk * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->lnb, stf + 3 * KMAX, nk * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    if (init) {
+        for (int i = 0; i < nk; ++i) st[2 * 3 * KMAX + i] = b[i];
+        GID_HIP(c, hipMemcpyAsync(c->binit64, st + 2 * 3 * KMAX, nk * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream));
+    }
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    return GID_OK;
+}
+
+bool colours_valid(const double* b, int nk) {
+    for (int i = 0; i < nk; ++i)
+        if (!std::isfinite(b[i]) || !(b[i] > 0.0)) return false;
+    return true;
+}
+
+// Enqueue the G outer iterations of one frame (everything between the per-frame
+// precompute and the output pass).  Returns the number of energy slots used.
+hipError_t enqueue_outer(gid_ctx* c, hipStream_t st, const Args& base, bool refine, bool record, int* nslots) {
+    int slot = 0;
+    hipError_t e = hipSuccess;
+    float* buf[2] = {c->pA, c->pB};
+    for (int g = 0; g < c->prm.gn_iters; ++g) {
+        Args a = base;
+        a.gn = g;
+        a.pnew = c->pA;
+        if ((e = GID_T(GID_KERNEL_GN_BUILD, launch_gn_build(a, st))) != hipSuccess) return e;
+        for (int i = 0; i < c->prm.pcg_iters; ++i) {
+            a.iter = i;
+            a.pold = (i == 0) ? c->pA : buf[(i - 1) & 1];
+            a.pnew = (i == 0) ? c->pA : buf[i & 1];
+            if ((e = GID_T(GID_KERNEL_MATVEC, launch_matvec(a, st))) != hipSuccess) return e;
+            if ((e = GID_T(GID_KERNEL_UPDATE, launch_update(a, st))) != hipSuccess) return e;
+        }
+        a.refine = refine ? 1 : 0;
+        a.add_delta = 1;
+        a.log_rz = 1;
+        a.iter = c->prm.pcg_iters - 1;
+        if ((e = GID_T(GID_KERNEL_APPLY_BSUM, launch_apply_bsum(a, c->nb_bs, st))) != hipSuccess) return e;
+        if (record) {
+            a.slot = slot++;
+            if ((e = GID_T(GID_KERNEL_ENERGY, launch_energy(a, st))) != hipSuccess) return e;
+            if ((e = launch_energy_finish(a, st)) != hipSuccess) return e;
+        }
+        if (refine) {
+            if ((e = GID_T(GID_KERNEL_BSOLVE, launch_bsolve(a, c->nb_bs, st))) != hipSuccess) return e;
+            if (record) {
+                a.slot = slot++;
+                if ((e = GID_T(GID_KERNEL_ENERGY, launch_energy(a, st))) != hipSuccess) return e;
+                if ((e = launch_energy_finish(a, st)) != hipSuccess) return e;
+            }
+        }
+    }
+    if (!record) {
+        Args a = base;
+        a.slot = FINAL_SLOT;
+        if ((e = GID_T(GID_KERNEL_ENERGY, launch_energy(a, st))) != hipSuccess) return e;
+        if ((e = launch_energy_finish(a, st)) != hipSuccess) return e;
+    }
+    *nslots = slot;
+    return hipSuccess;
+}
+
+gid_status run_outer(gid_ctx* c, const Args& base, bool refine, bool record, int* nslots) {
+    if (!c->prm.use_graph || c->profiling) {
+        GID_HIP(c, enqueue_outer(c, c->stream, base, refine, record, nslots));
+        return GID_OK;
+    }
+    const int key = (refine ? 1 : 0) | (base.temporal ? 2 : 0) | (record ? 4 : 0);
+    if (!c->graphs[key]) {
+        // capture on a private stream (the caller's may be the legacy null
+        // stream, which cannot be captured); the graph is launched on the caller's
+        if (!c->cap_stream) GID_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        GID_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_outer(c, c->cap_stream, base, refine, record, nslots);
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(c, GID_ERR_HIP, std::string("graph capture: ") +
+                                            hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipGraphExec_t ex = nullptr;
+        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(c, GID_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
+        c->graphs[key] = ex;
+    } else {
+        *nslots = record ? (c->prm.gn_iters * (refine ? 2 : 1)) : 0;
+    }
+    GID_HIP(c, hipGraphLaunch(c->graphs[key], c->stream));
+    return GID_OK;
+}
+
+gid_status check_params(const gid_params* p) {
+    if (!p || p->struct_size != sizeof(gid_params)) return GID_ERR_INVALID_ARG;
+    if (p->K < 1 || p->K > KMAX) return GID_ERR_INVALID_ARG;
+    if (p->gn_iters < 1 || p->gn_iters > 64) return GID_ERR_INVALID_ARG;
+    if (p->pcg_iters < 0 || p->pcg_iters > 4096) return GID_ERR_INVALID_ARG;
+    if (p->refine_mode < 0 || p->refine_mode > 2) return GID_ERR_INVALID_ARG;
+    if (p->cr_mode < 0 || p->cr_mode > 1) return GID_ERR_INVALID_ARG;
+    if (p->record_energy && 2 * p->gn_iters > GID_MAX_HALF_STEPS) return GID_ERR_INVALID_ARG;
+    if (!(p->eps_nonneg > 0.0f) || !(p->eps_irls > 0.0f)) return GID_ERR_INVALID_ARG;
+    if (!(p->lambda.p > 0.0f) || !(p->lambda.p <= 2.0f)) return GID_ERR_INVALID_ARG;
+    return GID_OK;
+}
+
+void release(gid_ctx* c) {
+    for (auto& e : c->ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    for (auto& g : c->graphs)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->h_elog) (void)hipHostFree(c->h_elog);
+    if (c->h_b64) (void)hipHostFree(c->h_b64);
+    if (c->h_small) (void)hipHostFree(c->h_small);
+    c->arena = nullptr;
+}
+
+gid_status check_frame_ready(gid_ctx* c) {
+    if (!c->colors_set) return fail(c, GID_ERR_STATE, "base colours not set");
+    return GID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gid_status gid_default_params(int32_t K, gid_params* out) {
+    if (!out || K < 1 || K > KMAX) return GID_ERR_INVALID_ARG;
+    gid_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.struct_size = sizeof(gid_params);
+    p.K = K;
+    p.lambda.data = 5000.0f;
+    p.lambda.cluster = 200.0f;
+    p.lambda.r_sparsity = 20.0f;
+    p.lambda.p = 1.0f;
+    p.lambda.r_consistency = 10.0f;
+    p.lambda.monochrome = 10.0f;
+    p.lambda.i_sparsity = 3.0f;
+    p.lambda.smoothness = 3.0f;
+    p.lambda.non_neg = 1000.0f;
+    p.lambda.ir = 10.0f;
+    p.lambda.cr = 100.0f;
+    p.eps_nonneg = 0.002f;
+    p.eps_irls = 0.002f;
+    p.retinex_k = 50.0f;
+    p.chroma_gate = 0.1;
+    p.chroma_floor = 1e-6;
+    p.gn_iters = 3;
+    p.pcg_iters = 8;
+    p.refine_mode = GID_REFINE_EVERY_STEP;
+    p.temporal = 1;
+    p.cr_mode = GID_CR_CHROMA;
+    p.record_energy = 0;
+    p.use_graph = 1;
+    *out = p;
+    return GID_OK;
+}
+
+gid_status gid_create(const gid_params* params, int32_t width, int32_t height, void* hip_stream,
+                      gid_ctx** out) {
+    if (!out) return GID_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (check_params(params) != GID_OK) return GID_ERR_INVALID_ARG;
+    if (width < 2 || height < 2 || (long long)width * height > (1LL << 28)) return GID_ERR_INVALID_ARG;
+    gid_ctx* c = new (std::nothrow) gid_ctx();
+    if (!c) return GID_ERR_OUT_OF_MEMORY;
+    c->prm = *params;
+    c->W = width;
+    c->H = height;
+    c->K = params->K;
+    c->n = params->K + 4;
+    c->ps = (long long)width * height;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return GID_ERR_HIP;
+    }
+    set_tiling(c, choose_ppt(width, height));
+    const int nsum = bstep_nsums(c->K);
+    c->part_stride = (long long)align_up((size_t)std::max<long long>((long long)NTERMS * NB_MAX,
+                                                                      (long long)nsum * NB_BS_MAX), 32);
+    // one arena: planes (exact stride width*height, each buffer 256-byte aligned),
+    // ids, small tables, reductions
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t fplane = sizeof(float) * (size_t)c->ps;
+    const size_t o_u = take(fplane * c->n), o_delta = take(fplane * c->n), o_res = take(fplane * c->n),
+                 o_pA = take(fplane * c->n), o_pB = take(fplane * c->n), o_q = take(fplane * c->n),
+                 o_minv = take(fplane * c->n), o_I = take(fplane * 3), o_wsr = take(fplane),
+                 o_tg = take(fplane * 4), o_Iprev = take(fplane * 3), o_rprev = take(fplane * 3);
+    const size_t o_ids = take((size_t)c->ps);
+    const size_t o_bf = take(sizeof(float) * 3 * KMAX);
+    const size_t o_lnb = take(sizeof(float) * 3 * KMAX);
+    const size_t o_b64 = take(sizeof(double) * 3 * KMAX);
+    const size_t o_lnb64 = take(sizeof(double) * 3 * KMAX);
+    const size_t o_binit = take(sizeof(double) * 3 * KMAX);
+    const size_t o_scal = take(sizeof(double) * NSCAL);
+    const size_t o_tick = take(sizeof(unsigned) * NRED);
+    const size_t o_elog = take(sizeof(double) * ELOG_SLOTS * ELOG_STRIDE);
+    const size_t o_bsum = take(sizeof(double) * bstep_nsums(KMAX));
+    const size_t o_part = take(sizeof(double) * (size_t)c->part_stride * NRED);
+    if (hipMalloc(&c->arena, off) != hipSuccess) {
+        delete c;
+        return GID_ERR_OUT_OF_MEMORY;
+    }
+    char* base = static_cast<char*>(c->arena);
+    auto fp = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
+    c->u = fp(o_u);
+    c->delta = fp(o_delta);
+    c->res = fp(o_res);
+    c->pA = fp(o_pA);
+    c->pB = fp(o_pB);
+    c->q = fp(o_q);
+    c->minv = fp(o_minv);
+    c->I = fp(o_I);
+    c->wsr = fp(o_wsr);
+    c->tg = fp(o_tg);
+    c->Iprev = fp(o_Iprev);
+    c->rprev = fp(o_rprev);
+    c->ids = reinterpret_cast<uint8_t*>(base + o_ids);
+    c->bf = reinterpret_cast<float*>(base + o_bf);
+    c->lnb = reinterpret_cast<float*>(base + o_lnb);
+    c->b64 = reinterpret_cast<double*>(base + o_b64);
+    c->lnb64 = reinterpret_cast<double*>(base + o_lnb64);
+    c->binit64 = reinterpret_cast<double*>(base + o_binit);
+    c->scal = reinterpret_cast<double*>(base + o_scal);
+    c->tickets = reinterpret_cast<unsigned*>(base + o_tick);
+    c->elog = reinterpret_cast<double*>(base + o_elog);
+    c->bsum = reinterpret_cast<double*>(base + o_bsum);
+    c->partials = reinterpret_cast<double*>(base + o_part);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_scal), sizeof(double) * NSCAL) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_elog), sizeof(double) * ELOG_SLOTS * ELOG_STRIDE) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_b64), sizeof(double) * 3 * KMAX) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_small), sizeof(double) * 8 * 3 * KMAX) != hipSuccess) {
+        release(c);
+        delete c;
+        return GID_ERR_OUT_OF_MEMORY;
+    }
+    // zero the whole workspace once (tickets must start at zero)
+    if (hipMemsetAsync(c->arena, 0, off, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        release(c);
+        delete c;
+        return GID_ERR_HIP;
+    }
+    *out = c;
+    return GID_OK;
+}
+
+gid_status gid_destroy(gid_ctx* c) {
+    if (!c) return GID_OK;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+    return GID_OK;
+}
+
+gid_status gid_set_base_colors(gid_ctx* c, const double* rgb) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!rgb || !colours_valid(rgb, 3 * c->K)) return fail(c, GID_ERR_INVALID_ARG, "base colours must be finite and > 0");
+    for (int i = 0; i < 3 * c->K; ++i) c->binit_host[i] = rgb[i];
+    gid_status s = upload_colours(c, rgb, true);
+    if (s != GID_OK) return s;
+    c->colors_set = true;
+    c->have_prev = false;
+    c->frame_index = 0;
+    return GID_OK;
+}
+
+gid_status gid_reset_clip(gid_ctx* c) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!c->colors_set) return fail(c, GID_ERR_STATE, "base colours not set");
+    return gid_set_base_colors(c, c->binit_host);
+}
+
+static gid_status load_frame_impl(gid_ctx* c, const float* frame, const uint8_t* ids, Args& a) {
+    a = base_args(c);
+    a.in_frame = frame;
+    a.in_ids = ids;
+    a.first = c->frame_index == 0;
+    a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
+    GID_HIP(c, launch_reset_frame(a, c->stream));
+    GID_HIP(c, GID_T(GID_KERNEL_SCAN, launch_scan(a, c->stream)));
+    GID_HIP(c, GID_T(GID_KERNEL_PRECOMPUTE, launch_precompute(a, c->stream)));
+    return GID_OK;
+}
+
+gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* ids, float* layers,
+                               double* b_out, gid_frame_stats* stats) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!frame || !ids) return fail(c, GID_ERR_INVALID_ARG, "frame and cluster ids are required");
+    gid_status s = check_frame_ready(c);
+    if (s != GID_OK) return s;
+    Args a;
+    if ((s = load_frame_impl(c, frame, ids, a)) != GID_OK) return s;
+    const int mode = c->prm.refine_mode;
+    const bool refine = mode == GID_REFINE_EVERY_STEP || (mode == GID_REFINE_FIRST_FRAME && c->frame_index == 0);
+    const bool record = c->prm.record_energy != 0;
+    int nslots = 0;
+    if ((s = run_outer(c, a, refine, record, &nslots)) != GID_OK) return s;
+    Args o = a;
+    o.out = layers;
+    GID_HIP(c, GID_T(GID_KERNEL_OUTPUT, launch_output(o, c->stream)));
+    GID_HIP(c, hipMemcpyAsync(c->h_elog, c->elog, sizeof(double) * ELOG_SLOTS * ELOG_STRIDE, hipMemcpyDeviceToHost,
+                              c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->h_b64, c->b64, sizeof(double) * 3 * c->K, hipMemcpyDeviceToHost, c->stream));
+    c->pending = true;
+    c->pend_b = b_out;
+    c->pend_stats = stats;
+    c->pend_nhalf = nslots;
+    c->pend_final_slot = record ? nslots - 1 : FINAL_SLOT;
+    c->pend_frame = c->frame_index;
+    c->pend_gn = c->prm.gn_iters;
+    c->pend_had_prev = c->have_prev;
+    c->frame_index += 1;
+    c->have_prev = true;
+    return GID_OK;
+}
+
+gid_status gid_synchronize(gid_ctx* c) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->ev_used) GID_HIP(c, collect_times(c));
+    if (!c->pending) return GID_OK;
+    c->pending = false;
+    if (c->h_scal[S_BADIN] != 0.0) {
+        // the frame was rejected on the device before any state changed
+        c->frame_index = c->pend_frame;
+        c->have_prev = c->pend_had_prev;
+        return fail(c, GID_ERR_NUMERIC, "frame has non-finite values or cluster ids outside [0, K); state unchanged");
+    }
+    const double* fin = c->h_elog + (long long)c->pend_final_slot * ELOG_STRIDE;
+    if (c->pend_b)
+        for (int i = 0; i < 3 * c->K; ++i) c->pend_b[i] = c->h_b64[i];
+    if (c->pend_stats) {
+        gid_frame_stats* st = c->pend_stats;
+        std::memset(st, 0, sizeof(*st));
+        st->energy_final = fin[0];
+        for (int v = 0; v < NTERMS; ++v) st->energy_terms[v] = fin[1 + v];
+        st->n_half = c->pend_nhalf;
+        for (int h = 0; h < c->pend_nhalf && h < GID_MAX_HALF_STEPS; ++h)
+            st->energy_half[h] = c->h_elog[(long long)h * ELOG_STRIDE];
+        for (int g = 0; g < 64; ++g) st->pcg_rz_last[g] = c->h_scal[S_RZ_LOG + g];
+        st->gn_done = c->pend_gn;
+        st->pcg_breakdowns = (int32_t)c->h_scal[S_BREAKDOWNS];
+        st->bstep_rejected = (int32_t)c->h_scal[S_BREJECT];
+        st->frame_index = c->pend_frame;
+    }
+    if (!std::isfinite(fin[0])) return fail(c, GID_ERR_NUMERIC, "final energy is not finite");
+    return GID_OK;
+}
+
+// ------------------------------------------------------------ single steps
+
+gid_status gid_load_frame(gid_ctx* c, const float* frame, const uint8_t* ids) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!frame || !ids) return fail(c, GID_ERR_INVALID_ARG, "frame and cluster ids are required");
+    gid_status s = check_frame_ready(c);
+    if (s != GID_OK) return s;
+    Args a;
+    if ((s = load_frame_impl(c, frame, ids, a)) != GID_OK) return s;
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    return GID_OK;
+}
+
+static Args step_args(gid_ctx* c) {
+    Args a = base_args(c);
+    a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
+    return a;
+}
+
+gid_status gid_set_state(gid_ctx* c, const float* u, const double* b) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!u) return fail(c, GID_ERR_INVALID_ARG, "u is required");
+    if (b && !colours_valid(b, 3 * c->K)) return fail(c, GID_ERR_INVALID_ARG, "colours must be finite and > 0");
+    GID_HIP(c, hipMemcpyAsync(c->u, u, sizeof(float) * c->ps * c->n, hipMemcpyDeviceToDevice, c->stream));
+    if (b) {
+        gid_status s = upload_colours(c, b, false);
+        if (s != GID_OK) return s;
+    }
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    return GID_OK;
+}
+
+gid_status gid_get_state(gid_ctx* c, float* u, double* b) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (u) GID_HIP(c, hipMemcpyAsync(u, c->u, sizeof(float) * c->ps * c->n, hipMemcpyDeviceToDevice, c->stream));
+    if (b) GID_HIP(c, hipMemcpyAsync(c->h_b64, c->b64, sizeof(double) * 3 * c->K, hipMemcpyDeviceToHost, c->stream));
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    if (b)
+        for (int i = 0; i < 3 * c->K; ++i) b[i] = c->h_b64[i];
+    return GID_OK;
+}
+
+gid_status gid_eval_energy(gid_ctx* c, double* e, double* terms) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    Args a = step_args(c);
+    a.slot = PROBE_SLOT;
+    GID_HIP(c, launch_energy(a, c->stream));
+    GID_HIP(c, launch_energy_finish(a, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->h_elog, c->elog, sizeof(double) * ELOG_SLOTS * ELOG_STRIDE, hipMemcpyDeviceToHost,
+                              c->stream));
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    const double* s = c->h_elog + (long long)PROBE_SLOT * ELOG_STRIDE;
+    if (e) *e = s[0];
+    if (terms)
+        for (int v = 0; v < NTERMS; ++v) terms[v] = s[1 + v];
+    return GID_OK;
+}
+
+gid_status gid_eval_rhs(gid_ctx* c, float* g, float* diag) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!g || !diag) return fail(c, GID_ERR_INVALID_ARG, "g and diag are required");
+    Args a = step_args(c);
+    a.debug = 1;
+    a.out = g;
+    a.out2 = diag;
+    GID_HIP(c, launch_gn_build(a, c->stream));
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    return GID_OK;
+}
+
+gid_status gid_apply_normal(gid_ctx* c, const float* p, float* q) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!p || !q) return fail(c, GID_ERR_INVALID_ARG, "p and q are required");
+    Args a = step_args(c);
+    a.debug = 1;
+    a.pdebug = p;
+    a.out = q;
+    GID_HIP(c, launch_matvec(a, c->stream));
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    return GID_OK;
+}
+
+gid_status gid_layer_step(gid_ctx* c, double* rz) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    Args a = step_args(c);
+    float* buf[2] = {c->pA, c->pB};
+    GID_HIP(c, launch_gn_build(a, c->stream));
+    for (int i = 0; i < c->prm.pcg_iters; ++i) {
+        a.iter = i;
+        a.pold = (i == 0) ? c->pA : buf[(i - 1) & 1];
+        a.pnew = (i == 0) ? c->pA : buf[i & 1];
+        GID_HIP(c, launch_matvec(a, c->stream));
+        GID_HIP(c, launch_update(a, c->stream));
+    }
+    a.refine = 0;
+    a.add_delta = 1;
+    a.log_rz = 1;
+    a.iter = c->prm.pcg_iters - 1;
+    a.gn = 0;
+    GID_HIP(c, launch_apply_bsum(a, c->nb_bs, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, c->stream));
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    if (rz) *rz = c->h_scal[S_RZ_LOG];
+    return GID_OK;
+}
+
+gid_status gid_bstep_sums(gid_ctx* c, double* A, double* h) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!A || !h) return fail(c, GID_ERR_INVALID_ARG, "A and h are required");
+    Args a = step_args(c);
+    a.refine = 1;
+    a.add_delta = 0;
+    GID_HIP(c, launch_apply_bsum(a, c->nb_bs, c->stream));
+    a.debug = 1;
+    GID_HIP(c, launch_bsolve(a, c->nb_bs, c->stream));
+    const int ns = bstep_nsums(c->K);
+    double* tmp = c->h_elog;   // large enough pinned buffer (ELOG_SLOTS * ELOG_STRIDE >= ns)
+    GID_HIP(c, hipMemcpyAsync(tmp, c->bsum, sizeof(double) * ns, hipMemcpyDeviceToHost, c->stream));
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    const int K = c->K;
+    for (int ch = 0; ch < 3; ++ch)
+        for (int k = 0; k < K; ++k) {
+            for (int l = 0; l < K; ++l) {
+                const int kk = std::min(k, l), ll = std::max(k, l);
+                A[(ch * K + k) * K + l] = tmp[ch * (K * (K + 1) / 2) + (kk * K - kk * (kk - 1) / 2) + (ll - kk)];
+            }
+            h[ch * K + k] = tmp[3 * K * (K + 1) / 2 + ch * K + k];
+        }
+    return GID_OK;
+}
+
+gid_status gid_base_step(gid_ctx* c, int32_t* accepted) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    Args a = step_args(c);
+    a.refine = 1;
+    a.add_delta = 0;
+    GID_HIP(c, launch_apply_bsum(a, c->nb_bs, c->stream));
+    GID_HIP(c, launch_bsolve(a, c->nb_bs, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, c->stream));
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    if (accepted) *accepted = c->h_scal[S_BACCEPT] != 0.0;
+    return GID_OK;
+}
+
+// --------------------------------------------------------- checkpoint
+
+namespace {
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t W, H, K, frame_index, have_prev, colors_set;
+};
+size_t state_bytes(const gid_ctx* c) {
+    return sizeof(StateHeader) + sizeof(double) * 2 * 3 * c->K + sizeof(float) * c->ps * (c->n + 6);
+}
+}  // namespace
+
+gid_status gid_save_state(gid_ctx* c, void* buf, size_t* inout) {
+    if (!c || !inout) return GID_ERR_INVALID_ARG;
+    const size_t need = state_bytes(c);
+    if (!buf) {
+        *inout = need;
+        return GID_OK;
+    }
+    if (*inout < need) return fail(c, GID_ERR_INVALID_ARG, "state buffer too small");
+    char* p = static_cast<char*>(buf);
+    StateHeader hd{STATE_MAGIC, 1, c->W, c->H, c->K, c->frame_index, c->have_prev, c->colors_set};
+    std::memcpy(p, &hd, sizeof(hd));
+    p += sizeof(hd);
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    GID_HIP(c, hipMemcpy(p, c->b64, sizeof(double) * 3 * c->K, hipMemcpyDeviceToHost));
+    p += sizeof(double) * 3 * c->K;
+    GID_HIP(c, hipMemcpy(p, c->binit64, sizeof(double) * 3 * c->K, hipMemcpyDeviceToHost));
+    p += sizeof(double) * 3 * c->K;
+    GID_HIP(c, hipMemcpy(p, c->u, sizeof(float) * c->ps * c->n, hipMemcpyDeviceToHost));
+    p += sizeof(float) * c->ps * c->n;
+    GID_HIP(c, hipMemcpy(p, c->Iprev, sizeof(float) * c->ps * 3, hipMemcpyDeviceToHost));
+    p += sizeof(float) * c->ps * 3;
+    GID_HIP(c, hipMemcpy(p, c->rprev, sizeof(float) * c->ps * 3, hipMemcpyDeviceToHost));
+    *inout = need;
+    return GID_OK;
+}
+
+gid_status gid_load_state(gid_ctx* c, const void* buf, size_t bytes) {
+    if (!c || !buf) return GID_ERR_INVALID_ARG;
+    if (bytes < state_bytes(c)) return fail(c, GID_ERR_INVALID_ARG, "state buffer too small");
+    const char* p = static_cast<const char*>(buf);
+    StateHeader hd;
+    std::memcpy(&hd, p, sizeof(hd));
+    if (hd.magic != STATE_MAGIC || hd.version != 1 || hd.W != c->W || hd.H != c->H || hd.K != c->K)
+        return fail(c, GID_ERR_INVALID_ARG, "state does not match this context");
+    p += sizeof(hd);
+    double b[3 * KMAX], b0[3 * KMAX];
+    std::memcpy(b, p, sizeof(double) * 3 * c->K);
+    p += sizeof(double) * 3 * c->K;
+    std::memcpy(b0, p, sizeof(double) * 3 * c->K);
+    p += sizeof(double) * 3 * c->K;
+    if (!colours_valid(b, 3 * c->K) || !colours_valid(b0, 3 * c->K))
+        return fail(c, GID_ERR_INVALID_ARG, "state holds invalid colours");
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    gid_status s = upload_colours(c, b0, true);
+    if (s != GID_OK) return s;
+    if ((s = upload_colours(c, b, false)) != GID_OK) return s;
+    for (int i = 0; i < 3 * c->K; ++i) c->binit_host[i] = b0[i];
+    GID_HIP(c, hipMemcpy(c->u, p, sizeof(float) * c->ps * c->n, hipMemcpyHostToDevice));
+    p += sizeof(float) * c->ps * c->n;
+    GID_HIP(c, hipMemcpy(c->Iprev, p, sizeof(float) * c->ps * 3, hipMemcpyHostToDevice));
+    p += sizeof(float) * c->ps * 3;
+    GID_HIP(c, hipMemcpy(c->rprev, p, sizeof(float) * c->ps * 3, hipMemcpyHostToDevice));
+    c->frame_index = hd.frame_index;
+    c->have_prev = hd.have_prev != 0;
+    c->colors_set = hd.colors_set != 0;
+    return GID_OK;
+}
+
+gid_status gid_set_profiling(gid_ctx* c, int32_t enable) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->ev_used) GID_HIP(c, collect_times(c));
+    c->profiling = enable != 0;
+    if (c->profiling)
+        for (int k = 0; k < GID_NUM_KERNEL_KINDS; ++k) {
+            c->kind_ms[k] = 0.0;
+            c->kind_n[k] = 0;
+        }
+    return GID_OK;
+}
+
+gid_status gid_get_kernel_times(gid_ctx* c, double* ms, int64_t* n) {
+    if (!c || !ms || !n) return GID_ERR_INVALID_ARG;
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->ev_used) GID_HIP(c, collect_times(c));
+    for (int k = 0; k < GID_NUM_KERNEL_KINDS; ++k) {
+        ms[k] = c->kind_ms[k];
+        n[k] = c->kind_n[k];
+    }
+    return GID_OK;
+}
+
+const char* gid_status_string(gid_status s) {
+    switch (s) {
+        case GID_OK: return "ok";
+        case GID_ERR_INVALID_ARG: return "invalid argument";
+        case GID_ERR_OUT_OF_MEMORY: return "out of memory";
+        case GID_ERR_HIP: return "HIP runtime error";
+        case GID_ERR_NUMERIC: return "non-finite value";
+        case GID_ERR_STATE: return "call out of order";
+        case GID_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* gid_last_error(const gid_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+}  // extern "C"

@@ -1,0 +1,292 @@
+"""ctypes binding of libgid (include/gid.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Device buffers are torch CUDA (ROCm) tensors; torch provides the
+memory and the current stream.  The library must be built (paper_1908_01961_amd.build);
+nothing here falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_float, c_int32, c_size_t, c_uint32, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgid.so")
+
+GID_OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error",
+          4: "non-finite value", 5: "call out of order", 6: "unsupported"}
+REFINE = {"off": 0, "first": 1, "every": 2}
+CR = {"chroma": 0, "literal": 1}
+KERNEL_KINDS = ("scan", "precompute", "gn_build", "matvec", "update", "apply_bsum", "bsolve", "energy",
+                "output")
+TERMS = ("data", "cluster", "rsparsity", "rconsist", "mono", "isparsity", "smooth", "nonneg")
+MAX_HALF = 128
+
+
+class GidLambdas(ctypes.Structure):
+    _fields_ = [(n, c_float) for n in ("data", "cluster", "r_sparsity", "p", "r_consistency",
+                                         "monochrome", "i_sparsity", "smoothness", "non_neg", "ir", "cr")]
+
+
+class GidParams(ctypes.Structure):
+    _fields_ = [("struct_size", c_uint32), ("K", c_int32), ("lambda_", GidLambdas),
+                ("eps_nonneg", c_float), ("eps_irls", c_float), ("retinex_k", c_float),
+                ("chroma_gate", c_double), ("chroma_floor", c_double),
+                ("gn_iters", c_int32), ("pcg_iters", c_int32), ("refine_mode", c_int32),
+                ("temporal", c_int32), ("cr_mode", c_int32), ("record_energy", c_int32),
+                ("use_graph", c_int32)]
+
+
+class GidFrameStats(ctypes.Structure):
+    _fields_ = [("energy_final", c_double), ("energy_terms", c_double * 8),
+                ("energy_half", c_double * MAX_HALF), ("pcg_rz_last", c_double * 64),
+                ("n_half", c_int32), ("gn_done", c_int32), ("pcg_breakdowns", c_int32),
+                ("bstep_rejected", c_int32), ("frame_index", c_int32)]
+
+    def to_dict(self) -> dict:
+        return dict(energy_final=self.energy_final,
+                    energy_terms=dict(zip(TERMS, list(self.energy_terms))),
+                    energy_half=list(self.energy_half[: self.n_half]),
+                    pcg_rz_last=list(self.pcg_rz_last[: self.gn_done]),
+                    gn_done=self.gn_done, pcg_breakdowns=self.pcg_breakdowns,
+                    bstep_rejected=self.bstep_rejected, frame_index=self.frame_index)
+
+
+_lib = None
+
+#: (name, restype, argtypes) of every exported call of gid.h
+SIGNATURES = [
+    ("gid_default_params", c_int32, [c_int32, POINTER(GidParams)]),
+    ("gid_create", c_int32, [POINTER(GidParams), c_int32, c_int32, c_void_p, POINTER(c_void_p)]),
+    ("gid_destroy", c_int32, [c_void_p]),
+    ("gid_set_base_colors", c_int32, [c_void_p, POINTER(c_double)]),
+    ("gid_reset_clip", c_int32, [c_void_p]),
+    ("gid_decompose_frame", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                                      POINTER(GidFrameStats)]),
+    ("gid_synchronize", c_int32, [c_void_p]),
+    ("gid_load_frame", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("gid_set_state", c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
+    ("gid_get_state", c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
+    ("gid_eval_energy", c_int32, [c_void_p, POINTER(c_double), POINTER(c_double)]),
+    ("gid_eval_rhs", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("gid_apply_normal", c_int32, [c_void_p, c_void_p, c_void_p]),
+    ("gid_layer_step", c_int32, [c_void_p, POINTER(c_double)]),
+    ("gid_bstep_sums", c_int32, [c_void_p, POINTER(c_double), POINTER(c_double)]),
+    ("gid_base_step", c_int32, [c_void_p, POINTER(c_int32)]),
+    ("gid_set_profiling", c_int32, [c_void_p, c_int32]),
+    ("gid_get_kernel_times", c_int32, [c_void_p, POINTER(c_double), POINTER(ctypes.c_int64)]),
+    ("gid_save_state", c_int32, [c_void_p, c_void_p, POINTER(c_size_t)]),
+    ("gid_load_state", c_int32, [c_void_p, c_void_p, c_size_t]),
+    ("gid_status_string", ctypes.c_char_p, [c_int32]),
+    ("gid_last_error", ctypes.c_char_p, [c_void_p]),
+]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgid.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgid.so is not built ({path}); run python -m paper_1908_01961_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class GidError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def default_params(K: int, **overrides) -> GidParams:
+    lib = load_library()
+    p = GidParams()
+    st = lib.gid_default_params(K, byref(p))
+    if st != GID_OK:
+        raise GidError(st, f"gid_default_params(K={K})")
+    for k, v in overrides.items():
+        if k == "refine_mode" and isinstance(v, str):
+            v = REFINE[v]
+        if k == "cr_mode" and isinstance(v, str):
+            v = CR[v]
+        if k.startswith("lam_"):
+            setattr(p.lambda_, k[4:], v)
+        else:
+            setattr(p, k, int(v) if isinstance(getattr(p, k), int) else v)
+    return p
+
+
+def _ptr(t, dtype, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+    return c_void_p(t.data_ptr())
+
+
+def _dbl(arr, n):
+    a = np.ascontiguousarray(np.asarray(arr, np.float64).reshape(-1))
+    if a.size != n:
+        raise ValueError(f"expected {n} values")
+    return a, a.ctypes.data_as(POINTER(c_double))
+
+
+class Solver:
+    """One libgid context: frames of width x height with K base colours."""
+
+    def __init__(self, width: int, height: int, params: GidParams | int, stream=None):
+        import torch
+        self.lib = load_library()
+        if isinstance(params, int):
+            params = default_params(params)
+        self.params = params
+        self.W, self.H, self.K = int(width), int(height), int(params.K)
+        self.n = self.K + 4
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = c_void_p()
+        st = self.lib.gid_create(byref(params), self.W, self.H, c_void_p(stream.cuda_stream), byref(h))
+        if st != GID_OK:
+            raise GidError(st, f"gid_create({self.W}x{self.H}, K={self.K})")
+        self.h = h
+        self._stats = GidFrameStats()
+        self._b = np.zeros(3 * self.K)
+
+    def _check(self, st, what):
+        if st != GID_OK:
+            raise GidError(st, f"{what}: {self.lib.gid_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.gid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- clip control
+    def set_base_colors(self, b):
+        a, p = _dbl(b, 3 * self.K)
+        self._check(self.lib.gid_set_base_colors(self.h, p), "gid_set_base_colors")
+
+    def reset_clip(self):
+        self._check(self.lib.gid_reset_clip(self.h), "gid_reset_clip")
+
+    # -- full frame
+    def decompose_frame_async(self, frame, ids, layers=None):
+        """Enqueue one frame; outputs are valid after synchronize()."""
+        import torch
+        f = _ptr(frame, torch.float32, (3, self.H, self.W), "frame")
+        i = _ptr(ids, torch.uint8, (self.H, self.W), "ids")
+        lp = _ptr(layers, torch.float32, (self.n, self.H, self.W), "layers") if layers is not None else None
+        self._b = np.zeros(3 * self.K)
+        self._check(self.lib.gid_decompose_frame(self.h, f, i, lp, self._b.ctypes.data_as(POINTER(c_double)),
+                                                 byref(self._stats)), "gid_decompose_frame")
+
+    def synchronize(self):
+        self._check(self.lib.gid_synchronize(self.h), "gid_synchronize")
+        return self._b.reshape(self.K, 3).copy(), self._stats.to_dict()
+
+    def decompose_frame(self, frame, ids, layers=None):
+        self.decompose_frame_async(frame, ids, layers)
+        return self.synchronize()
+
+    # -- single steps
+    def load_frame(self, frame, ids):
+        import torch
+        f = _ptr(frame, torch.float32, (3, self.H, self.W), "frame")
+        i = _ptr(ids, torch.uint8, (self.H, self.W), "ids")
+        self._check(self.lib.gid_load_frame(self.h, f, i), "gid_load_frame")
+
+    def set_state(self, u, b=None):
+        import torch
+        up = _ptr(u, torch.float32, (self.n, self.H, self.W), "u")
+        if b is not None:
+            arr, bp = _dbl(b, 3 * self.K)
+        else:
+            arr, bp = None, None
+        self._check(self.lib.gid_set_state(self.h, up, bp), "gid_set_state")
+
+    def get_state(self):
+        import torch
+        u = torch.empty((self.n, self.H, self.W), dtype=torch.float32, device="cuda")
+        b = np.zeros(3 * self.K)
+        self._check(self.lib.gid_get_state(self.h, _ptr(u, torch.float32, u.shape, "u"),
+                                           b.ctypes.data_as(POINTER(c_double))), "gid_get_state")
+        return u, b.reshape(self.K, 3)
+
+    def eval_energy(self):
+        e = c_double()
+        terms = (c_double * 8)()
+        self._check(self.lib.gid_eval_energy(self.h, byref(e), terms), "gid_eval_energy")
+        return e.value, dict(zip(TERMS, list(terms)))
+
+    def eval_rhs(self):
+        import torch
+        g = torch.empty((self.n, self.H, self.W), dtype=torch.float32, device="cuda")
+        d = torch.empty_like(g)
+        self._check(self.lib.gid_eval_rhs(self.h, c_void_p(g.data_ptr()), c_void_p(d.data_ptr())), "gid_eval_rhs")
+        return g, d
+
+    def apply_normal(self, p):
+        import torch
+        pp = _ptr(p, torch.float32, (self.n, self.H, self.W), "p")
+        q = torch.empty_like(p)
+        self._check(self.lib.gid_apply_normal(self.h, pp, c_void_p(q.data_ptr())), "gid_apply_normal")
+        return q
+
+    def layer_step(self):
+        rz = c_double()
+        self._check(self.lib.gid_layer_step(self.h, byref(rz)), "gid_layer_step")
+        return rz.value
+
+    def bstep_sums(self):
+        K = self.K
+        A = np.zeros(3 * K * K)
+        h = np.zeros(3 * K)
+        self._check(self.lib.gid_bstep_sums(self.h, A.ctypes.data_as(POINTER(c_double)),
+                                            h.ctypes.data_as(POINTER(c_double))), "gid_bstep_sums")
+        return A.reshape(3, K, K), h.reshape(3, K)
+
+    def base_step(self):
+        ok = c_int32()
+        self._check(self.lib.gid_base_step(self.h, byref(ok)), "gid_base_step")
+        return bool(ok.value)
+
+    # -- kernel timing
+    def set_profiling(self, enable: bool):
+        self._check(self.lib.gid_set_profiling(self.h, int(bool(enable))), "gid_set_profiling")
+
+    def kernel_times(self) -> dict:
+        nk = len(KERNEL_KINDS)
+        ms = (c_double * nk)()
+        n = (ctypes.c_int64 * nk)()
+        self._check(self.lib.gid_get_kernel_times(self.h, ms, n), "gid_get_kernel_times")
+        return {k: dict(ms=ms[i], launches=n[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+    # -- checkpoint
+    def save_state(self) -> bytes:
+        n = c_size_t()
+        self._check(self.lib.gid_save_state(self.h, None, byref(n)), "gid_save_state")
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self.lib.gid_save_state(self.h, buf, byref(n)), "gid_save_state")
+        return buf.raw[: n.value]
+
+    def load_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self.lib.gid_load_state(self.h, buf, len(blob)), "gid_load_state")

@@ -1,0 +1,306 @@
+"""GPU path versus the FP64 oracle, through the C ABI (libgid via the binding).
+
+Tolerances: single kernels fed the same FP32 state are compared with the
+oracle evaluated at that state (FP32 per-pixel arithmetic against FP64: 1e-5 of
+the plane's largest magnitude; FP64 sums and energies: 1e-9 relative).  Whole
+schedules (fixed G x P, same inputs): layers within 1e-3 absolute and the final
+energy within 1e-4 relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.basecolor import bstep, bstep_sums
+from oracle.energy import chromaticity, energy_terms, prepare_frame
+from oracle.gauss_newton import apply_normal, jacobi_diag, linearise, rhs
+from scenes import downsample_clip, make_clip, workload_clip
+
+pytestmark = pytest.mark.gpu
+
+TERMS = ("data", "cluster", "rsparsity", "rconsist", "mono", "isparsity", "smooth", "nonneg")
+P = O.default_params()
+
+
+def _say(*msg):
+    print("[gpu-case]", *msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_01961_amd as G
+    G.load_library()
+    return _t
+
+
+def _solver(torch, W, H, K, **kw):
+    import paper_1908_01961_amd as G
+    prm = G.default_params(K, **kw)
+    return G.Solver(W, H, prm)
+
+
+def _dev(torch, a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def _u_np(u):
+    return u.detach().cpu().numpy().astype(np.float64)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(1e-30, np.abs(b).max()))
+
+
+# --------------------------------------------------------------- single steps
+
+@pytest.fixture(scope="module")
+def step_case(torch):
+    """A 70x45 video frame pair (ragged tiles), K = 5, temporal prior on."""
+    _say("step_case 70x45 K=5 seed 61")
+    c = make_clip(70, 45, 5, 2, 61)
+    s = _solver(torch, 70, 45, 5, temporal=1)
+    s.set_base_colors(c.b_init)
+    # frame 0 through the full schedule, then frame 1 loaded with the temporal prior
+    s.decompose_frame(_dev(torch, c.frames[0]), _dev(torch, c.ids[0]))
+    u0, b0 = s.get_state()
+    s.load_frame(_dev(torch, c.frames[1]), _dev(torch, c.ids[1]))
+    rng = np.random.default_rng(5)
+    u = _u_np(u0) + 0.02 * rng.standard_normal(u0.shape)
+    u_t = _dev(torch, u.astype(np.float32))
+    s.set_state(u_t, b0)
+    u32 = u.astype(np.float32).astype(np.float64)
+    prev_C = chromaticity(c.frames[0].astype(np.float64), P)
+    prev_r = _u_np(u0)[:3]
+    fd = prepare_frame(c.frames[1], c.ids[1], P, prev_C, prev_r)
+    return dict(c=c, s=s, u=u32, b=b0, fd=fd, u_t=u_t)
+
+
+def test_energy_single_step(step_case):
+    s, u, b, fd = step_case["s"], step_case["u"], step_case["b"], step_case["fd"]
+    E, terms = s.eval_energy()
+    ref = energy_terms(u, b, fd, P)
+    for k in TERMS:
+        assert terms[k] == pytest.approx(ref[k], rel=1e-9, abs=1e-9), k
+    assert E == pytest.approx(sum(ref.values()), rel=1e-9)
+
+
+def test_rhs_and_diag_single_step(step_case):
+    s, u, b, fd = step_case["s"], step_case["u"], step_case["b"], step_case["fd"]
+    g, d = s.eval_rhs()
+    lin = linearise(u, b, fd, P)
+    g_ref, d_ref = rhs(lin), jacobi_diag(lin)
+    g, d = _u_np(g), _u_np(d)
+    for v in range(u.shape[0]):
+        assert _rel(g[v], g_ref[v]) < 1e-5, ("g", v, _rel(g[v], g_ref[v]))
+        assert _rel(d[v], d_ref[v]) < 1e-5, ("diag", v)
+
+
+def test_apply_normal_single_step(torch, step_case):
+    s, u, b, fd = step_case["s"], step_case["u"], step_case["b"], step_case["fd"]
+    rng = np.random.default_rng(7)
+    p = rng.standard_normal(u.shape).astype(np.float32)
+    q = _u_np(s.apply_normal(_dev(torch, p)))
+    q_ref = apply_normal(p.astype(np.float64), linearise(u, b, fd, P))
+    for v in range(u.shape[0]):
+        assert _rel(q[v], q_ref[v]) < 1e-5, ("q", v, _rel(q[v], q_ref[v]))
+
+
+def test_bstep_sums_single_step(step_case):
+    s, u, b, fd = step_case["s"], step_case["u"], step_case["b"], step_case["fd"]
+    A, h = s.bstep_sums()
+    A_ref, h_ref = bstep_sums(u, b, fd.I, P)
+    assert _rel(A, A_ref) < 1e-9 and _rel(h, h_ref) < 1e-9
+
+
+def test_base_step_single_step(torch, step_case):
+    s, u, b, fd, c = step_case["s"], step_case["u"], step_case["b"], step_case["fd"], step_case["c"]
+    s.set_state(step_case["u_t"], b)
+    ok = s.base_step()
+    _, b_gpu = s.get_state()
+    b_ref, ok_ref = bstep(u, b, c.b_init, fd.I, P)
+    assert ok == ok_ref
+    assert np.abs(b_gpu - b_ref).max() < 1e-9
+    s.set_state(step_case["u_t"], b)
+
+
+def test_layer_step_single_step(torch, step_case):
+    s, u, b, fd = step_case["s"], step_case["u"], step_case["b"], step_case["fd"]
+    s.set_state(step_case["u_t"], b)
+    rz = s.layer_step()
+    u_gpu, _ = s.get_state()
+    lin = linearise(u, b, fd, P)
+    d, info = O.pcg(lin, 8)
+    un = u + d
+    assert np.abs(_u_np(u_gpu) - un).max() < 1e-4
+    assert rz == pytest.approx(info["rz"], rel=1e-3)
+    s.set_state(step_case["u_t"], b)
+
+
+# -------------------------------------------------------------- whole schedules
+
+def _run_gpu_clip(torch, clip, G_, P_, nframes, temporal, refine="every", **kw):
+    s = _solver(torch, clip.width, clip.height, clip.K, gn_iters=G_, pcg_iters=P_, temporal=int(temporal),
+                refine_mode=refine, record_energy=1, **kw)
+    s.set_base_colors(clip.b_init)
+    out = []
+    layers = torch.empty((clip.K + 4, clip.height, clip.width), dtype=torch.float32, device="cuda")
+    for t in range(nframes):
+        b, st = s.decompose_frame(_dev(torch, clip.frames[t]), _dev(torch, clip.ids[t]), layers)
+        u, _ = s.get_state()
+        out.append(dict(layers=_u_np(layers), u=_u_np(u), b=b, stats=st))
+    s.close()
+    return out
+
+
+def _compare(gpu, orc, tol_layer=1e-3, tol_e=1e-4):
+    worst = {}
+    for t, (g, o) in enumerate(zip(gpu, orc)):
+        R_o = np.exp(o.u[:3])
+        dR = np.abs(g["layers"][:3] - R_o).max()
+        dT = np.abs(g["layers"][3:] - o.u[3:]).max()
+        db = np.abs(g["b"] - o.b).max()
+        eg, eo = g["stats"]["energy_final"], o.energy
+        rel = abs(eg - eo) / abs(eo)
+        worst = dict(frame=t, dR=dR, dT=dT, db=db, Erel=rel)
+        _say(f"frame {t}: |dR|={dR:.2e} |dT|={dT:.2e} |db|={db:.2e} Erel={rel:.2e}")
+        assert dR <= tol_layer and dT <= tol_layer and db <= tol_layer, worst
+        assert rel <= tol_e, worst
+    return worst
+
+
+def test_schedule_single_frame_64x48(torch):
+    _say("schedule single_64x48_k4 5x10")
+    c = workload_clip("single_64x48_k4")
+    gpu = _run_gpu_clip(torch, c, 5, 10, 1, False)
+    orc = O.decompose_clip(c.frames, c.ids, c.b_init, P, 5, 10, temporal=False)
+    _compare(gpu, orc)
+    eh = gpu[0]["stats"]["energy_half"]
+    assert len(eh) == 10
+    for a, (_, b) in zip(eh, orc[0].energies):
+        assert a == pytest.approx(b, rel=1e-4)
+
+
+def test_schedule_video_160x120(torch):
+    _say("schedule video 160x120 K=6 5 frames 3x8 temporal")
+    c = make_clip(160, 120, 6, 5, 200)
+    gpu = _run_gpu_clip(torch, c, 3, 8, 5, True)
+    orc = O.decompose_clip(c.frames, c.ids, c.b_init, P, 3, 8, temporal=True, nframes=5)
+    _compare(gpu, orc)
+
+
+def test_schedule_video_640x480_two_frames(torch):
+    _say("schedule video_640x480_k6 first 2 frames 3x8 temporal (full size)")
+    c = workload_clip("video_640x480_k6", nframes=2)
+    gpu = _run_gpu_clip(torch, c, 3, 8, 2, True)
+    orc = O.decompose_clip(c.frames, c.ids, c.b_init, P, 3, 8, temporal=True, nframes=2)
+    _compare(gpu, orc)
+
+
+def test_schedule_1080p_downsampled_96x54(torch):
+    _say("schedule 1920x1080 K=10 scene, 96x54 area-averaged copy, 3 frames")
+    full = make_clip(1920, 1080, 10, 3, 500, amp=0.35, supersample=False)
+    c = downsample_clip(full, 20)
+    gpu = _run_gpu_clip(torch, c, 3, 8, 3, True)
+    orc = O.decompose_clip(c.frames, c.ids, c.b_init, P, 3, 8, temporal=True, nframes=3)
+    _compare(gpu, orc)
+
+
+@pytest.mark.parametrize("W,H,K", [(2, 2, 2), (70, 45, 1), (33, 17, 16), (129, 9, 3)])
+def test_schedule_edge_shapes(torch, W, H, K):
+    _say(f"edge shape {W}x{H} K={K}")
+    c = make_clip(W, H, K, 2, 900 + W + K)
+    gpu = _run_gpu_clip(torch, c, 2, 6, 2, True)
+    orc = O.decompose_clip(c.frames, c.ids, c.b_init, P, 2, 6, temporal=True, nframes=2)
+    _compare(gpu, orc)
+
+
+def test_refine_modes_and_literal_cr(torch):
+    _say("refine modes first/off and literal chromaticity term, 96x64 K=4 3 frames")
+    c = make_clip(96, 64, 4, 3, 321)
+    for mode in ("first", "off"):
+        gpu = _run_gpu_clip(torch, c, 2, 8, 3, True, refine=mode)
+        orc = O.decompose_clip(c.frames, c.ids, c.b_init, P, 2, 8, temporal=True, refine_mode=mode, nframes=3)
+        _compare(gpu, orc)
+    pl = O.default_params(cr_mode="literal")
+    gpu = _run_gpu_clip(torch, c, 2, 8, 2, True, cr_mode="literal")
+    orc = O.decompose_clip(c.frames, c.ids, c.b_init, pl, 2, 8, temporal=True, nframes=2)
+    _compare(gpu, orc)
+
+
+# --------------------------------------------------- determinism, graph, resume
+
+def test_graph_replay_matches_direct_launches_bitwise(torch):
+    _say("graph vs direct launches, 128x96 K=6 4 frames")
+    c = make_clip(128, 96, 6, 4, 77)
+    a = _run_gpu_clip(torch, c, 3, 8, 4, True, use_graph=1)
+    b = _run_gpu_clip(torch, c, 3, 8, 4, True, use_graph=0)
+    a2 = _run_gpu_clip(torch, c, 3, 8, 4, True, use_graph=1)
+    for x, y, z in zip(a, b, a2):
+        assert np.array_equal(x["layers"], y["layers"]) and np.array_equal(x["layers"], z["layers"])
+        assert x["stats"]["energy_final"] == y["stats"]["energy_final"] == z["stats"]["energy_final"]
+
+
+def test_checkpoint_resume_is_bitwise(torch):
+    _say("checkpoint / resume, 96x64 K=4 4 frames")
+    c = make_clip(96, 64, 4, 4, 88)
+    full = _run_gpu_clip(torch, c, 2, 6, 4, True)
+    s = _solver(torch, 96, 64, 4, gn_iters=2, pcg_iters=6, record_energy=1)
+    s.set_base_colors(c.b_init)
+    for t in range(2):
+        s.decompose_frame(_dev(torch, c.frames[t]), _dev(torch, c.ids[t]))
+    blob = s.save_state()
+    s.close()
+    s2 = _solver(torch, 96, 64, 4, gn_iters=2, pcg_iters=6, record_energy=1)
+    s2.load_state(blob)
+    layers = torch.empty((8, 64, 96), dtype=torch.float32, device="cuda")
+    for t in range(2, 4):
+        b, st = s2.decompose_frame(_dev(torch, c.frames[t]), _dev(torch, c.ids[t]), layers)
+        assert np.array_equal(_u_np(layers), full[t]["layers"])
+        assert st["energy_final"] == full[t]["stats"]["energy_final"]
+
+
+def test_bad_input_frame_is_rejected_and_state_kept(torch):
+    _say("non-finite frame and out-of-range ids are rejected")
+    import paper_1908_01961_amd as G
+    c = make_clip(64, 32, 3, 3, 5)
+    s = _solver(torch, 64, 32, 3, gn_iters=2, pcg_iters=4)
+    s.set_base_colors(c.b_init)
+    s.decompose_frame(_dev(torch, c.frames[0]), _dev(torch, c.ids[0]))
+    u_before, b_before = s.get_state()
+    bad = c.frames[1].copy()
+    bad[1, 3, 4] = np.nan
+    with pytest.raises(G.GidError) as ei:
+        s.decompose_frame(_dev(torch, bad), _dev(torch, c.ids[1]))
+    assert ei.value.status == 4
+    ids_bad = c.ids[1].copy()
+    ids_bad[0, 0] = 3
+    with pytest.raises(G.GidError):
+        s.decompose_frame(_dev(torch, c.frames[1]), _dev(torch, ids_bad))
+    u_after, b_after = s.get_state()
+    assert torch.equal(u_before, u_after) and np.array_equal(b_before, b_after)
+    # the clip continues as if the bad frames had not been offered
+    _, st = s.decompose_frame(_dev(torch, c.frames[1]), _dev(torch, c.ids[1]))
+    assert st["frame_index"] == 1
+
+
+def test_zero_operator_hits_pcg_breakdown_guard(torch):
+    _say("zero operator -> PCG breakdown guard")
+    zero = dict(lam_data=0.0, lam_cluster=0.0, lam_r_sparsity=0.0, lam_r_consistency=0.0,
+                lam_monochrome=0.0, lam_i_sparsity=0.0, lam_smoothness=0.0, lam_non_neg=0.0)
+    c = make_clip(64, 16, 2, 1, 3)
+    s = _solver(torch, 64, 16, 2, gn_iters=1, pcg_iters=4, refine_mode="off", **zero)
+    s.set_base_colors(c.b_init)
+    s.load_frame(_dev(torch, c.frames[0]), _dev(torch, c.ids[0]))
+    u0, _ = s.get_state()
+    s.layer_step()
+    u1, _ = s.get_state()
+    assert torch.equal(u0, u1)
