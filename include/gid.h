@@ -151,6 +151,13 @@ gid_status gid_load_frame(gid_ctx *ctx, const float *frame_dev, const uint8_t *c
  * device) and b (K x 3 doubles, host, may be NULL to keep the current colours). */
 gid_status gid_set_state(gid_ctx *ctx, const float *u_dev, const double *b_host);
 
+/* Continue a clip from an external decomposition: frame_prev_dev is the
+ * previous frame (3 planes, device) and r_prev_dev its final log-reflectance
+ * (3 planes, device).  The next frame is solved as a continuation (temporal
+ * prior against these when params.temporal), starting from the state set by
+ * gid_set_state.  Errors: GID_ERR_INVALID_ARG (NULL), GID_ERR_STATE (no colours). */
+gid_status gid_set_prev_frame(gid_ctx *ctx, const float *frame_prev_dev, const float *r_prev_dev);
+
 /* Copy out the unknowns (same layout as gid_set_state); b_host may be NULL.
  * Synchronous. */
 gid_status gid_get_state(gid_ctx *ctx, float *u_dev, double *b_host);
@@ -192,6 +199,45 @@ gid_status gid_set_profiling(gid_ctx *ctx, int32_t enable);
 /* Accumulated milliseconds and launch counts per kernel kind (arrays of
  * GID_NUM_KERNEL_KINDS entries, host). */
 gid_status gid_get_kernel_times(gid_ctx *ctx, double *ms_out, int64_t *launches_out);
+
+/* ---- batches of clips of uneven size ----
+ * A batch groups contexts (each with its own frame size and K) that share the
+ * stream, the schedule (gn_iters, pcg_iters, refine_mode) and record_energy = 0.
+ * Every kernel of a batch step is one launch over all active clips: each
+ * workgroup finds its clip in a device descriptor table and runs that clip's
+ * kernel body; reductions stay per clip.  With use_graph the outer iterations
+ * of a step are replayed from a graph cached per set of active clips. */
+typedef struct gid_batch gid_batch;
+
+/* Group n (1..64) distinct contexts into a batch.  Tune the contexts (gid_autotune,
+ * gid_set_workgroups) before creating the batch.  Errors: GID_ERR_INVALID_ARG
+ * (mismatched streams or schedules, record_energy on, duplicates). */
+gid_status gid_batch_create(gid_ctx *const *ctxs, int32_t n, gid_batch **out);
+gid_status gid_batch_destroy(gid_batch *b);
+
+/* One step: decompose the next frame of every clip i with frames_dev[i] != NULL
+ * (clips that have run out of frames pass NULL and are skipped).  ids_dev[i] as
+ * for gid_decompose_frame; layers_dev may be NULL or hold NULL entries.  Each
+ * step must be followed by gid_batch_synchronize before the next. */
+gid_status gid_batch_decompose(gid_batch *b, const float *const *frames_dev,
+                               const uint8_t *const *ids_dev, float *const *layers_dev);
+
+/* Wait for the step; energies_out (n doubles, may be NULL) receives each active
+ * clip's final energy (NaN for skipped clips).  GID_ERR_NUMERIC if a clip's frame
+ * was rejected (its state is unchanged) or its energy is not finite. */
+gid_status gid_batch_synchronize(gid_batch *b, double *energies_out);
+const char *gid_batch_last_error(const gid_batch *b);
+
+/* ---- launch-shape autotuner ----
+ * Choose the number of workgroups of the per-pixel launches for this context's
+ * (width, height, K) by timing the stencil kernels of a layer step on the device
+ * over candidates 64..2048.  cache_path (may be NULL) is a text file of
+ * "width height K workgroups" lines: a cached choice is reused, a new one appended.
+ * Synchronous; changes no solver state other than scratch vectors. */
+gid_status gid_autotune(gid_ctx *ctx, const char *cache_path, int32_t *workgroups_out);
+/* Set / read the workgroup count directly (8..2048, rounded to a multiple of 8). */
+gid_status gid_set_workgroups(gid_ctx *ctx, int32_t workgroups);
+int32_t gid_get_workgroups(const gid_ctx *ctx);
 
 /* ---- checkpoint / resume ---- */
 /* Serialise the solver state (unknowns, colours, previous-frame data, frame

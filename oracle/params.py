@@ -31,6 +31,12 @@ class OracleParams:
     chroma_gate: float = 0.1       # reading: temporal pairs count when |dC|_2 < 0.1
     chroma_floor: float = 1e-6     # reading: chromaticity is white below this intensity
     cr_mode: str = "chroma"        # "chroma" (anchored to the initial estimate) or "literal"
+    # Storage precision of the unknowns between steps: "f64", or "f32" to round
+    # them where a single-precision implementation stores them (the initial
+    # state and after every layer step).  The discrete IRLS branches (T > 0 for
+    # the non-negativity weight) are decided on the stored state, so an FP32
+    # implementation is compared with the "f32" setting; all arithmetic stays FP64.
+    state_precision: str = "f64"
 
 
 def default_params(**kw) -> OracleParams:

@@ -25,6 +25,13 @@ from .gauss_newton import linearise, pcg
 from .params import OracleParams
 
 
+def store(u: np.ndarray, p: OracleParams) -> np.ndarray:
+    """The unknowns as stored between steps (see OracleParams.state_precision)."""
+    if p.state_precision == "f32":
+        return np.asarray(u, np.float32).astype(np.float64)
+    return u
+
+
 def init_state(I: np.ndarray, ids: np.ndarray, b: np.ndarray) -> np.ndarray:
     I = np.asarray(I, np.float64)
     K = np.asarray(b).shape[0]
@@ -57,7 +64,7 @@ def decompose_frame(I, ids, b, b_init, p: OracleParams, G: int, P: int, *, u0=No
     """
     fd = prepare_frame(I, ids, p, *(prev if prev is not None else (None, None)))
     b = np.asarray(b, np.float64).copy()
-    u = init_state(fd.I, fd.ids, b) if u0 is None else np.asarray(u0, np.float64).copy()
+    u = store(init_state(fd.I, fd.ids, b), p) if u0 is None else np.asarray(u0, np.float64).copy()
     energies, infos = [], []
     for _ in range(G):
         lin = linearise(u, b, fd, p)
@@ -67,7 +74,7 @@ def decompose_frame(I, ids, b, b_init, p: OracleParams, G: int, P: int, *, u0=No
             delta, info = direct_step(lin), {"rz": float("nan"), "iters": -1}
         else:
             raise ValueError(solver)
-        u = u + delta
+        u = store(u + delta, p)
         infos.append(info)
         if record:
             energies.append(("T", total_energy(u, b, fd, p)))

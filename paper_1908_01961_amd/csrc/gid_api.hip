@@ -7,8 +7,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "gid_internal.h"
 
@@ -18,7 +21,8 @@ namespace {
 
 constexpr int FINAL_SLOT = ELOG_SLOTS - 2;   // energy of the frame when half-steps are not recorded
 constexpr int PROBE_SLOT = ELOG_SLOTS - 1;   // single-step energy evaluation
-constexpr int NB_MAX = 1024;                 // workgroups of a per-pixel launch (partials per reduction)
+constexpr int NB_MAX = 1024;                 // default cap on workgroups of a per-pixel launch
+constexpr int NB_TUNE_MAX = 2048;            // largest workgroup count the autotuner may choose
 constexpr int NB_BS_MAX = 512;               // workgroups of the apply + base-colour-sum pass
 constexpr uint32_t STATE_MAGIC = 0x67696431u; // "gid1"
 
@@ -36,7 +40,7 @@ struct gid_ctx {
     // device workspace
     float *u = nullptr, *delta = nullptr, *res = nullptr, *pA = nullptr, *pB = nullptr, *q = nullptr,
           *minv = nullptr, *I = nullptr, *wsr = nullptr, *tg = nullptr, *Iprev = nullptr,
-          *rprev = nullptr, *bf = nullptr, *lnb = nullptr;
+          *rprev = nullptr, *bf = nullptr, *lnb = nullptr, *bcf = nullptr;
     uint8_t* ids = nullptr;
     double *b64 = nullptr, *lnb64 = nullptr, *binit64 = nullptr, *scal = nullptr, *partials = nullptr,
            *elog = nullptr, *bsum = nullptr;
@@ -117,7 +121,28 @@ hipError_t collect_times(gid_ctx* c) {
     return hipSuccess;
 }
 
-#define GID_T(KIND, CALL) timed(c, KIND, [&]() { return (CALL); })
+// Profiling kind of a kernel (-1: not timed).
+int kind_of(Kern k) {
+    switch (k) {
+        case KN_SCAN: return GID_KERNEL_SCAN;
+        case KN_PRECOMPUTE: return GID_KERNEL_PRECOMPUTE;
+        case KN_GN_BUILD: return GID_KERNEL_GN_BUILD;
+        case KN_MATVEC: return GID_KERNEL_MATVEC;
+        case KN_UPDATE: return GID_KERNEL_UPDATE;
+        case KN_APPLY_BSUM: return GID_KERNEL_APPLY_BSUM;
+        case KN_BSOLVE: return GID_KERNEL_BSOLVE;
+        case KN_ENERGY: return GID_KERNEL_ENERGY;
+        case KN_OUTPUT: return GID_KERNEL_OUTPUT;
+        default: return -1;
+    }
+}
+
+// Launch kernel k of one clip on stream st (timed when profiling is on).
+hipError_t L1(gid_ctx* c, hipStream_t st, Kern k, const Args& a, const Step& s) {
+    const int kind = kind_of(k);
+    if (kind < 0) return launch_kernel(k, a, s, st);
+    return timed(c, kind, [&]() { return launch_kernel(k, a, s, st); });
+}
 
 Lam make_lam(const gid_params& p) {
     Lam L;
@@ -151,15 +176,15 @@ Args base_args(const gid_ctx* c) {
     a.nty = c->nty;
     a.ntiles = c->ntiles;
     a.nblocks = c->nblocks;
+    a.nb_bs = c->nb_bs;
     a.ps = c->ps;
     a.lam = make_lam(c->prm);
     a.cr_literal = c->prm.cr_mode == GID_CR_LITERAL;
-    a.add_delta = 1;
     a.u = c->u;
     a.delta = c->delta;
     a.res = c->res;
-    a.pold = c->pA;
-    a.pnew = c->pA;
+    a.pA = c->pA;
+    a.pB = c->pB;
     a.q = c->q;
     a.minv = c->minv;
     a.I = c->I;
@@ -170,6 +195,7 @@ Args base_args(const gid_ctx* c) {
     a.rprev = c->rprev;
     a.bf = c->bf;
     a.lnb = c->lnb;
+    a.bcf = c->bcf;
     a.b64 = c->b64;
     a.lnb64 = c->lnb64;
     a.binit64 = c->binit64;
@@ -182,15 +208,9 @@ Args base_args(const gid_ctx* c) {
     return a;
 }
 
-// Tile height: the smallest rows-per-thread that keeps the grid near 4096
-// workgroups (enough to fill 256 CUs several times, few enough partials).
-int choose_ppt(int W, int H) {
-    const int ntx = (W + TX - 1) / TX;
-    for (int ppt : {1, 2, 4, 8}) {
-        const int nty = (H + TYW * ppt - 1) / (TYW * ppt);
-        if ((long long)ntx * nty <= 4096) return ppt;
-    }
-    return 8;
+// Pixel rows per thread in a tile.
+int choose_ppt(int, int) {
+    return 1;   // the halo-staged stencil kernels work on 64 x 4 tiles
 }
 
 // Each workgroup of a per-pixel launch owns a contiguous chunk of tiles; the
@@ -207,28 +227,34 @@ void set_tiling(gid_ctx* c, int ppt) {
     c->nb_bs = std::min(c->nblocks, NB_BS_MAX);
 }
 
-// Upload colours b (K x 3 doubles) into b64 / bf / lnb / lnb64 (and the initial
-// estimate when init is true) through the pinned staging buffer.
+// Use nb workgroups for the per-pixel launches (rounded to a multiple of 8, at
+// most one per tile); cached graphs are rebuilt on their next use.
+void set_nblocks(gid_ctx* c, int nb) {
+    nb = std::max(8, std::min(nb, (int)align_up((size_t)c->ntiles, 8)));
+    c->nblocks = (int)align_up((size_t)nb, 8);
+    c->nb_bs = std::min(c->nblocks, NB_BS_MAX);
+    for (auto& g : c->graphs)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Upload colours b (K x 3 doubles, and the initial estimate when init is true)
+// through the pinned staging buffer; the derived tables are computed on the
+// device by the same routine the base-colour solve uses.
 gid_status upload_colours(gid_ctx* c, const double* b, bool init) {
     const int nk = 3 * c->K;
     GID_HIP(c, hipStreamSynchronize(c->stream));
     double* st = c->h_small;
-    float* stf = reinterpret_cast<float*>(st + 4 * 3 * KMAX);
     for (int i = 0; i < nk; ++i) {
         st[i] = b[i];
-        st[3 * KMAX + i] = std::log(b[i]);
-        stf[i] = (float)b[i];
-        stf[3 * KMAX + i] = (float)std::log(b[i]);
+        st[3 * KMAX + i] = b[i];
     }
     GID_HIP(c, hipMemcpyAsync(c->b64, st, nk * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    GID_HIP(c, hipMemcpyAsync(c->lnb64, st + 3 * KMAX, nk * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    GID_HIP(c, hipMemcpyAsync(c->bf, stf, nk * sizeof(float), hipMemcpyHostToDevice, c->stream));
-    GID_HIP(c, hipMemcpyAsync(c->lnb, stf + 3 * KMAX, nk * sizeof(float), hipMemcpyHostToDevice, c->stream));
-    if (init) {
-        for (int i = 0; i < nk; ++i) st[2 * 3 * KMAX + i] = b[i];
-        GID_HIP(c, hipMemcpyAsync(c->binit64, st + 2 * 3 * KMAX, nk * sizeof(double), hipMemcpyHostToDevice,
-                                  c->stream));
-    }
+    if (init)
+        GID_HIP(c, hipMemcpyAsync(c->binit64, st + 3 * KMAX, nk * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    GID_HIP(c, launch_kernel(KN_TABLES, base_args(c), Step{}, c->stream));
     GID_HIP(c, hipStreamSynchronize(c->stream));
     return GID_OK;
 }
@@ -240,50 +266,72 @@ bool colours_valid(const double* b, int nk) {
 }
 
 // Enqueue the G outer iterations of one frame (everything between the per-frame
-// precompute and the output pass).  Returns the number of energy slots used.
-hipError_t enqueue_outer(gid_ctx* c, hipStream_t st, const Args& base, bool refine, bool record, int* nslots) {
+// precompute and the output pass) through launch(kern, step); used for one clip
+// and for batches.  Returns the number of energy slots used.
+template <typename LaunchFn>
+hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& launch, int* nslots) {
     int slot = 0;
     hipError_t e = hipSuccess;
-    float* buf[2] = {c->pA, c->pB};
-    for (int g = 0; g < c->prm.gn_iters; ++g) {
-        Args a = base;
-        a.gn = g;
-        a.pnew = c->pA;
-        if ((e = GID_T(GID_KERNEL_GN_BUILD, launch_gn_build(a, st))) != hipSuccess) return e;
-        for (int i = 0; i < c->prm.pcg_iters; ++i) {
-            a.iter = i;
-            a.pold = (i == 0) ? c->pA : buf[(i - 1) & 1];
-            a.pnew = (i == 0) ? c->pA : buf[i & 1];
-            if ((e = GID_T(GID_KERNEL_MATVEC, launch_matvec(a, st))) != hipSuccess) return e;
-            if ((e = GID_T(GID_KERNEL_UPDATE, launch_update(a, st))) != hipSuccess) return e;
+    for (int g = 0; g < G; ++g) {
+        Step s{};
+        s.gn = g;
+        if ((e = launch(KN_GN_BUILD, s)) != hipSuccess) return e;
+        for (int i = 0; i < P; ++i) {
+            s.iter = i;
+            if ((e = launch(KN_MATVEC, s)) != hipSuccess) return e;
+            if ((e = launch(KN_UPDATE, s)) != hipSuccess) return e;
         }
-        a.refine = refine ? 1 : 0;
-        a.add_delta = 1;
-        a.log_rz = 1;
-        a.iter = c->prm.pcg_iters - 1;
-        if ((e = GID_T(GID_KERNEL_APPLY_BSUM, launch_apply_bsum(a, c->nb_bs, st))) != hipSuccess) return e;
+        s.refine = refine ? 1 : 0;
+        s.add_delta = 1;
+        s.log_rz = 1;
+        s.iter = P - 1;
+        if ((e = launch(KN_APPLY_BSUM, s)) != hipSuccess) return e;
         if (record) {
-            a.slot = slot++;
-            if ((e = GID_T(GID_KERNEL_ENERGY, launch_energy(a, st))) != hipSuccess) return e;
-            if ((e = launch_energy_finish(a, st)) != hipSuccess) return e;
+            s.slot = slot++;
+            if ((e = launch(KN_ENERGY, s)) != hipSuccess) return e;
+            if ((e = launch(KN_ENERGY_FINISH, s)) != hipSuccess) return e;
         }
         if (refine) {
-            if ((e = GID_T(GID_KERNEL_BSOLVE, launch_bsolve(a, c->nb_bs, st))) != hipSuccess) return e;
+            if ((e = launch(KN_BSOLVE, s)) != hipSuccess) return e;
             if (record) {
-                a.slot = slot++;
-                if ((e = GID_T(GID_KERNEL_ENERGY, launch_energy(a, st))) != hipSuccess) return e;
-                if ((e = launch_energy_finish(a, st)) != hipSuccess) return e;
+                s.slot = slot++;
+                if ((e = launch(KN_ENERGY, s)) != hipSuccess) return e;
+                if ((e = launch(KN_ENERGY_FINISH, s)) != hipSuccess) return e;
             }
         }
     }
     if (!record) {
-        Args a = base;
-        a.slot = FINAL_SLOT;
-        if ((e = GID_T(GID_KERNEL_ENERGY, launch_energy(a, st))) != hipSuccess) return e;
-        if ((e = launch_energy_finish(a, st)) != hipSuccess) return e;
+        Step s{};
+        s.slot = FINAL_SLOT;
+        if ((e = launch(KN_ENERGY, s)) != hipSuccess) return e;
+        if ((e = launch(KN_ENERGY_FINISH, s)) != hipSuccess) return e;
     }
     *nslots = slot;
     return hipSuccess;
+}
+
+hipError_t enqueue_outer(gid_ctx* c, hipStream_t st, const Args& base, bool refine, bool record, int* nslots) {
+    return enqueue_schedule(c->prm.gn_iters, c->prm.pcg_iters, refine, record,
+                            [&](Kern k, const Step& s) { return L1(c, st, k, base, s); }, nslots);
+}
+
+// Capture a schedule into a graph on a private stream (the caller's may be the
+// legacy null stream, which cannot be captured); the graph runs on any stream.
+template <typename EnqueueFn>
+hipError_t capture_graph(hipStream_t* cap, EnqueueFn&& enqueue, hipGraphExec_t* out) {
+    hipError_t e;
+    if (!*cap && (e = hipStreamCreateWithFlags(cap, hipStreamNonBlocking)) != hipSuccess) return e;
+    hipGraph_t g = nullptr;
+    if ((e = hipStreamBeginCapture(*cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    hipError_t e1 = enqueue(*cap);
+    hipError_t e2 = hipStreamEndCapture(*cap, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return e1 != hipSuccess ? e1 : e2;
+    }
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
 }
 
 gid_status run_outer(gid_ctx* c, const Args& base, bool refine, bool record, int* nslots) {
@@ -293,22 +341,11 @@ gid_status run_outer(gid_ctx* c, const Args& base, bool refine, bool record, int
     }
     const int key = (refine ? 1 : 0) | (base.temporal ? 2 : 0) | (record ? 4 : 0);
     if (!c->graphs[key]) {
-        // capture on a private stream (the caller's may be the legacy null
-        // stream, which cannot be captured); the graph is launched on the caller's
-        if (!c->cap_stream) GID_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-        hipGraph_t g = nullptr;
-        GID_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_outer(c, c->cap_stream, base, refine, record, nslots);
-        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return fail(c, GID_ERR_HIP, std::string("graph capture: ") +
-                                            hipGetErrorString(e != hipSuccess ? e : e2));
-        }
         hipGraphExec_t ex = nullptr;
-        hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e3 != hipSuccess) return fail(c, GID_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
+        hipError_t e = capture_graph(&c->cap_stream, [&](hipStream_t cs) {
+            return enqueue_outer(c, cs, base, refine, record, nslots);
+        }, &ex);
+        if (e != hipSuccess) return fail(c, GID_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
         c->graphs[key] = ex;
     } else {
         *nslots = record ? (c->prm.gn_iters * (refine ? 2 : 1)) : 0;
@@ -414,7 +451,7 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     }
     set_tiling(c, choose_ppt(width, height));
     const int nsum = bstep_nsums(c->K);
-    c->part_stride = (long long)align_up((size_t)std::max<long long>((long long)NTERMS * NB_MAX,
+    c->part_stride = (long long)align_up((size_t)std::max<long long>((long long)NTERMS * NB_TUNE_MAX,
                                                                       (long long)nsum * NB_BS_MAX), 32);
     // one arena: planes (exact stride width*height, each buffer 256-byte aligned),
     // ids, small tables, reductions
@@ -432,6 +469,7 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     const size_t o_ids = take((size_t)c->ps);
     const size_t o_bf = take(sizeof(float) * 3 * KMAX);
     const size_t o_lnb = take(sizeof(float) * 3 * KMAX);
+    const size_t o_bcf = take(sizeof(float) * 3 * KMAX);
     const size_t o_b64 = take(sizeof(double) * 3 * KMAX);
     const size_t o_lnb64 = take(sizeof(double) * 3 * KMAX);
     const size_t o_binit = take(sizeof(double) * 3 * KMAX);
@@ -461,6 +499,7 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     c->ids = reinterpret_cast<uint8_t*>(base + o_ids);
     c->bf = reinterpret_cast<float*>(base + o_bf);
     c->lnb = reinterpret_cast<float*>(base + o_lnb);
+    c->bcf = reinterpret_cast<float*>(base + o_bcf);
     c->b64 = reinterpret_cast<double*>(base + o_b64);
     c->lnb64 = reinterpret_cast<double*>(base + o_lnb64);
     c->binit64 = reinterpret_cast<double*>(base + o_binit);
@@ -519,9 +558,10 @@ static gid_status load_frame_impl(gid_ctx* c, const float* frame, const uint8_t*
     a.in_ids = ids;
     a.first = c->frame_index == 0;
     a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
-    GID_HIP(c, launch_reset_frame(a, c->stream));
-    GID_HIP(c, GID_T(GID_KERNEL_SCAN, launch_scan(a, c->stream)));
-    GID_HIP(c, GID_T(GID_KERNEL_PRECOMPUTE, launch_precompute(a, c->stream)));
+    const Step s{};
+    GID_HIP(c, L1(c, c->stream, KN_RESET, a, s));
+    GID_HIP(c, L1(c, c->stream, KN_SCAN, a, s));
+    GID_HIP(c, L1(c, c->stream, KN_PRECOMPUTE, a, s));
     return GID_OK;
 }
 
@@ -540,7 +580,7 @@ gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* id
     if ((s = run_outer(c, a, refine, record, &nslots)) != GID_OK) return s;
     Args o = a;
     o.out = layers;
-    GID_HIP(c, GID_T(GID_KERNEL_OUTPUT, launch_output(o, c->stream)));
+    GID_HIP(c, L1(c, c->stream, KN_OUTPUT, o, Step{}));
     GID_HIP(c, hipMemcpyAsync(c->h_elog, c->elog, sizeof(double) * ELOG_SLOTS * ELOG_STRIDE, hipMemcpyDeviceToHost,
                               c->stream));
     GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, c->stream));
@@ -623,6 +663,19 @@ gid_status gid_set_state(gid_ctx* c, const float* u, const double* b) {
     return GID_OK;
 }
 
+gid_status gid_set_prev_frame(gid_ctx* c, const float* frame_prev, const float* r_prev) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!frame_prev || !r_prev) return fail(c, GID_ERR_INVALID_ARG, "previous frame and reflectance are required");
+    gid_status s = check_frame_ready(c);
+    if (s != GID_OK) return s;
+    GID_HIP(c, hipMemcpyAsync(c->Iprev, frame_prev, sizeof(float) * 3 * c->ps, hipMemcpyDeviceToDevice, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->rprev, r_prev, sizeof(float) * 3 * c->ps, hipMemcpyDeviceToDevice, c->stream));
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    c->have_prev = true;
+    c->frame_index = std::max(c->frame_index, 1);
+    return GID_OK;
+}
+
 gid_status gid_get_state(gid_ctx* c, float* u, double* b) {
     if (!c) return GID_ERR_INVALID_ARG;
     if (u) GID_HIP(c, hipMemcpyAsync(u, c->u, sizeof(float) * c->ps * c->n, hipMemcpyDeviceToDevice, c->stream));
@@ -636,16 +689,17 @@ gid_status gid_get_state(gid_ctx* c, float* u, double* b) {
 gid_status gid_eval_energy(gid_ctx* c, double* e, double* terms) {
     if (!c) return GID_ERR_INVALID_ARG;
     Args a = step_args(c);
-    a.slot = PROBE_SLOT;
-    GID_HIP(c, launch_energy(a, c->stream));
-    GID_HIP(c, launch_energy_finish(a, c->stream));
+    Step s{};
+    s.slot = PROBE_SLOT;
+    GID_HIP(c, launch_kernel(KN_ENERGY, a, s, c->stream));
+    GID_HIP(c, launch_kernel(KN_ENERGY_FINISH, a, s, c->stream));
     GID_HIP(c, hipMemcpyAsync(c->h_elog, c->elog, sizeof(double) * ELOG_SLOTS * ELOG_STRIDE, hipMemcpyDeviceToHost,
                               c->stream));
     GID_HIP(c, hipStreamSynchronize(c->stream));
-    const double* s = c->h_elog + (long long)PROBE_SLOT * ELOG_STRIDE;
-    if (e) *e = s[0];
+    const double* pr = c->h_elog + (long long)PROBE_SLOT * ELOG_STRIDE;
+    if (e) *e = pr[0];
     if (terms)
-        for (int v = 0; v < NTERMS; ++v) terms[v] = s[1 + v];
+        for (int v = 0; v < NTERMS; ++v) terms[v] = pr[1 + v];
     return GID_OK;
 }
 
@@ -653,10 +707,11 @@ gid_status gid_eval_rhs(gid_ctx* c, float* g, float* diag) {
     if (!c) return GID_ERR_INVALID_ARG;
     if (!g || !diag) return fail(c, GID_ERR_INVALID_ARG, "g and diag are required");
     Args a = step_args(c);
-    a.debug = 1;
+    Step s{};
+    s.debug = 1;
     a.out = g;
     a.out2 = diag;
-    GID_HIP(c, launch_gn_build(a, c->stream));
+    GID_HIP(c, launch_kernel(KN_GN_BUILD, a, s, c->stream));
     GID_HIP(c, hipStreamSynchronize(c->stream));
     return GID_OK;
 }
@@ -665,10 +720,11 @@ gid_status gid_apply_normal(gid_ctx* c, const float* p, float* q) {
     if (!c) return GID_ERR_INVALID_ARG;
     if (!p || !q) return fail(c, GID_ERR_INVALID_ARG, "p and q are required");
     Args a = step_args(c);
-    a.debug = 1;
+    Step s{};
+    s.debug = 1;
     a.pdebug = p;
     a.out = q;
-    GID_HIP(c, launch_matvec(a, c->stream));
+    GID_HIP(c, launch_kernel(KN_MATVEC, a, s, c->stream));
     GID_HIP(c, hipStreamSynchronize(c->stream));
     return GID_OK;
 }
@@ -676,21 +732,19 @@ gid_status gid_apply_normal(gid_ctx* c, const float* p, float* q) {
 gid_status gid_layer_step(gid_ctx* c, double* rz) {
     if (!c) return GID_ERR_INVALID_ARG;
     Args a = step_args(c);
-    float* buf[2] = {c->pA, c->pB};
-    GID_HIP(c, launch_gn_build(a, c->stream));
+    Step s{};
+    GID_HIP(c, launch_kernel(KN_GN_BUILD, a, s, c->stream));
     for (int i = 0; i < c->prm.pcg_iters; ++i) {
-        a.iter = i;
-        a.pold = (i == 0) ? c->pA : buf[(i - 1) & 1];
-        a.pnew = (i == 0) ? c->pA : buf[i & 1];
-        GID_HIP(c, launch_matvec(a, c->stream));
-        GID_HIP(c, launch_update(a, c->stream));
+        s.iter = i;
+        GID_HIP(c, launch_kernel(KN_MATVEC, a, s, c->stream));
+        GID_HIP(c, launch_kernel(KN_UPDATE, a, s, c->stream));
     }
-    a.refine = 0;
-    a.add_delta = 1;
-    a.log_rz = 1;
-    a.iter = c->prm.pcg_iters - 1;
-    a.gn = 0;
-    GID_HIP(c, launch_apply_bsum(a, c->nb_bs, c->stream));
+    s.refine = 0;
+    s.add_delta = 1;
+    s.log_rz = 1;
+    s.iter = c->prm.pcg_iters - 1;
+    s.gn = 0;
+    GID_HIP(c, launch_kernel(KN_APPLY_BSUM, a, s, c->stream));
     GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, c->stream));
     GID_HIP(c, hipStreamSynchronize(c->stream));
     if (rz) *rz = c->h_scal[S_RZ_LOG];
@@ -701,11 +755,11 @@ gid_status gid_bstep_sums(gid_ctx* c, double* A, double* h) {
     if (!c) return GID_ERR_INVALID_ARG;
     if (!A || !h) return fail(c, GID_ERR_INVALID_ARG, "A and h are required");
     Args a = step_args(c);
-    a.refine = 1;
-    a.add_delta = 0;
-    GID_HIP(c, launch_apply_bsum(a, c->nb_bs, c->stream));
-    a.debug = 1;
-    GID_HIP(c, launch_bsolve(a, c->nb_bs, c->stream));
+    Step s{};
+    s.refine = 1;
+    GID_HIP(c, launch_kernel(KN_APPLY_BSUM, a, s, c->stream));
+    s.debug = 1;
+    GID_HIP(c, launch_kernel(KN_BSOLVE, a, s, c->stream));
     const int ns = bstep_nsums(c->K);
     double* tmp = c->h_elog;   // large enough pinned buffer (ELOG_SLOTS * ELOG_STRIDE >= ns)
     GID_HIP(c, hipMemcpyAsync(tmp, c->bsum, sizeof(double) * ns, hipMemcpyDeviceToHost, c->stream));
@@ -725,10 +779,10 @@ gid_status gid_bstep_sums(gid_ctx* c, double* A, double* h) {
 gid_status gid_base_step(gid_ctx* c, int32_t* accepted) {
     if (!c) return GID_ERR_INVALID_ARG;
     Args a = step_args(c);
-    a.refine = 1;
-    a.add_delta = 0;
-    GID_HIP(c, launch_apply_bsum(a, c->nb_bs, c->stream));
-    GID_HIP(c, launch_bsolve(a, c->nb_bs, c->stream));
+    Step s{};
+    s.refine = 1;
+    GID_HIP(c, launch_kernel(KN_APPLY_BSUM, a, s, c->stream));
+    GID_HIP(c, launch_kernel(KN_BSOLVE, a, s, c->stream));
     GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, c->stream));
     GID_HIP(c, hipStreamSynchronize(c->stream));
     if (accepted) *accepted = c->h_scal[S_BACCEPT] != 0.0;
@@ -828,6 +882,295 @@ gid_status gid_get_kernel_times(gid_ctx* c, double* ms, int64_t* n) {
     }
     return GID_OK;
 }
+
+// ---------------------------------------------------------------- batches
+
+struct gid_batch {
+    std::vector<gid_ctx*> clips;
+    std::vector<int> nb_snapshot;      // per-clip workgroup counts the batch was built with
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int kb = 0;
+    void* dmem = nullptr;              // device: Args[n], wg_pix[n+1], wg_bs[n+1]
+    Args* d_args = nullptr;
+    int* d_wg = nullptr;
+    Args* h_args = nullptr;            // pinned staging of the same
+    int* h_wg = nullptr;
+    double* h_out = nullptr;           // pinned: per clip final energy and input-check flag
+    std::map<std::pair<unsigned long long, int>, hipGraphExec_t> graphs;
+    std::vector<int> active;           // clips of the pending step
+    bool pending = false;
+    std::string err;
+};
+
+namespace {
+gid_status bfail(gid_batch* b, gid_status s, const std::string& m) {
+    if (b) b->err = m;
+    return s;
+}
+#define GID_BHIP(b, call)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return bfail((b), GID_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void batch_release(gid_batch* b) {
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->dmem) (void)hipFree(b->dmem);
+    if (b->h_args) (void)hipHostFree(b->h_args);
+    if (b->h_wg) (void)hipHostFree(b->h_wg);
+    if (b->h_out) (void)hipHostFree(b->h_out);
+}
+}  // namespace
+
+gid_status gid_batch_create(gid_ctx* const* ctxs, int32_t n, gid_batch** out) {
+    if (!out || !ctxs || n < 1 || n > 64) return GID_ERR_INVALID_ARG;
+    *out = nullptr;
+    const gid_ctx* c0 = ctxs[0];
+    if (!c0) return GID_ERR_INVALID_ARG;
+    for (int i = 0; i < n; ++i) {
+        const gid_ctx* c = ctxs[i];
+        if (!c || c->stream != c0->stream || c->device != c0->device) return GID_ERR_INVALID_ARG;
+        if (c->prm.gn_iters != c0->prm.gn_iters || c->prm.pcg_iters != c0->prm.pcg_iters ||
+            c->prm.refine_mode != c0->prm.refine_mode || c->prm.record_energy != 0)
+            return GID_ERR_INVALID_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return GID_ERR_INVALID_ARG;
+    }
+    gid_batch* b = new (std::nothrow) gid_batch();
+    if (!b) return GID_ERR_OUT_OF_MEMORY;
+    b->stream = c0->stream;
+    for (int i = 0; i < n; ++i) {
+        b->clips.push_back(ctxs[i]);
+        b->nb_snapshot.push_back(ctxs[i]->nblocks);
+        b->kb = std::max(b->kb, ctxs[i]->K);
+    }
+    const size_t args_bytes = align_up(sizeof(Args) * n, 256);
+    if (hipMalloc(&b->dmem, args_bytes + sizeof(int) * 2 * (n + 1)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->h_args), sizeof(Args) * n) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->h_wg), sizeof(int) * 2 * (n + 1)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(double) * 2 * n) != hipSuccess) {
+        batch_release(b);
+        delete b;
+        return GID_ERR_OUT_OF_MEMORY;
+    }
+    b->d_args = static_cast<Args*>(b->dmem);
+    b->d_wg = reinterpret_cast<int*>(static_cast<char*>(b->dmem) + args_bytes);
+    *out = b;
+    return GID_OK;
+}
+
+gid_status gid_batch_destroy(gid_batch* b) {
+    if (!b) return GID_OK;
+    (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
+    delete b;
+    return GID_OK;
+}
+
+gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const uint8_t* const* ids,
+                               float* const* layers) {
+    if (!b || !frames || !ids) return bfail(b, GID_ERR_INVALID_ARG, "frames and ids are required");
+    if (b->pending) return bfail(b, GID_ERR_STATE, "synchronize the previous batch step first");
+    const int n = (int)b->clips.size();
+    std::vector<int> act;
+    unsigned long long mask = 0;
+    int first_count = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!frames[i]) continue;
+        gid_ctx* c = b->clips[i];
+        if (!ids[i]) return bfail(b, GID_ERR_INVALID_ARG, "ids missing for an active clip");
+        if (!c->colors_set) return bfail(b, GID_ERR_STATE, "base colours not set for a clip");
+        if (c->nblocks != b->nb_snapshot[i]) return bfail(b, GID_ERR_STATE, "a clip was retuned after gid_batch_create");
+        act.push_back(i);
+        mask |= 1ull << i;
+        first_count += c->frame_index == 0;
+    }
+    if (act.empty()) return GID_OK;
+    const int mode = b->clips[0]->prm.refine_mode;
+    if (mode == GID_REFINE_FIRST_FRAME && first_count != 0 && first_count != (int)act.size())
+        return bfail(b, GID_ERR_UNSUPPORTED, "refine-first-frame needs the active clips at the same frame");
+    const bool refine = mode == GID_REFINE_EVERY_STEP || (mode == GID_REFINE_FIRST_FRAME && first_count > 0);
+    const int na = (int)act.size();
+    int* wg_pix = b->h_wg;
+    int* wg_bs = b->h_wg + (na + 1);
+    wg_pix[0] = wg_bs[0] = 0;
+    for (int j = 0; j < na; ++j) {
+        gid_ctx* c = b->clips[act[j]];
+        Args a = base_args(c);
+        a.in_frame = frames[act[j]];
+        a.in_ids = ids[act[j]];
+        a.out = layers ? layers[act[j]] : nullptr;
+        a.first = c->frame_index == 0;
+        a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
+        b->h_args[j] = a;
+        wg_pix[j + 1] = wg_pix[j] + c->nblocks;
+        wg_bs[j + 1] = wg_bs[j] + c->nb_bs;
+    }
+    hipStream_t st = b->stream;
+    GID_BHIP(b, hipMemcpyAsync(b->d_args, b->h_args, sizeof(Args) * na, hipMemcpyHostToDevice, st));
+    GID_BHIP(b, hipMemcpyAsync(b->d_wg, b->h_wg, sizeof(int) * 2 * (na + 1), hipMemcpyHostToDevice, st));
+    BatchGrid g;
+    g.args = b->d_args;
+    g.wg_pix = b->d_wg;
+    g.wg_bs = b->d_wg + (na + 1);
+    g.nclips = na;
+    g.total_pix = wg_pix[na];
+    g.total_bs = wg_bs[na];
+    g.kb = b->kb;
+    const Step s0{};
+    GID_BHIP(b, launch_batch(KN_RESET, g, s0, st));
+    GID_BHIP(b, launch_batch(KN_SCAN, g, s0, st));
+    GID_BHIP(b, launch_batch(KN_PRECOMPUTE, g, s0, st));
+    const gid_params& prm = b->clips[0]->prm;
+    auto enqueue = [&](hipStream_t cs) {
+        int ns = 0;
+        return enqueue_schedule(prm.gn_iters, prm.pcg_iters, refine, false,
+                                [&](Kern k, const Step& s) { return launch_batch(k, g, s, cs); }, &ns);
+    };
+    if (prm.use_graph) {
+        const auto key = std::make_pair(mask, refine ? 1 : 0);
+        auto it = b->graphs.find(key);
+        if (it == b->graphs.end()) {
+            hipGraphExec_t ex = nullptr;
+            hipError_t e = capture_graph(&b->cap_stream, enqueue, &ex);
+            if (e != hipSuccess) return bfail(b, GID_ERR_HIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+            it = b->graphs.emplace(key, ex).first;
+        }
+        GID_BHIP(b, hipGraphLaunch(it->second, st));
+    } else {
+        GID_BHIP(b, enqueue(st));
+    }
+    GID_BHIP(b, launch_batch(KN_OUTPUT, g, s0, st));
+    for (int j = 0; j < na; ++j) {
+        gid_ctx* c = b->clips[act[j]];
+        GID_BHIP(b, hipMemcpyAsync(b->h_out + 2 * act[j], c->elog + (long long)FINAL_SLOT * ELOG_STRIDE,
+                                   sizeof(double), hipMemcpyDeviceToHost, st));
+        GID_BHIP(b, hipMemcpyAsync(b->h_out + 2 * act[j] + 1, c->scal + S_BADIN, sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
+        c->frame_index += 1;
+        c->have_prev = true;
+    }
+    b->active = act;
+    b->pending = true;
+    return GID_OK;
+}
+
+gid_status gid_batch_synchronize(gid_batch* b, double* energies) {
+    if (!b) return GID_ERR_INVALID_ARG;
+    GID_BHIP(b, hipStreamSynchronize(b->stream));
+    if (!b->pending) return GID_OK;
+    b->pending = false;
+    const int n = (int)b->clips.size();
+    if (energies)
+        for (int i = 0; i < n; ++i) energies[i] = std::nan("");
+    gid_status st = GID_OK;
+    for (int i : b->active) {
+        if (b->h_out[2 * i + 1] != 0.0) {
+            gid_ctx* c = b->clips[i];      // frame rejected on the device: no state changed
+            c->frame_index -= 1;
+            c->have_prev = c->frame_index > 0;
+            st = GID_ERR_NUMERIC;
+            continue;
+        }
+        if (energies) energies[i] = b->h_out[2 * i];
+        if (!std::isfinite(b->h_out[2 * i])) st = GID_ERR_NUMERIC;
+    }
+    if (st != GID_OK) b->err = "a clip's frame was rejected or its energy is not finite";
+    return st;
+}
+
+const char* gid_batch_last_error(const gid_batch* b) { return b ? b->err.c_str() : "no batch"; }
+
+// ------------------------------------------------------------- autotuner
+
+namespace {
+bool cache_lookup(const char* path, int W, int H, int K, int* nb) {
+    FILE* f = path ? std::fopen(path, "r") : nullptr;
+    if (!f) return false;
+    int w, h, k, v;
+    bool found = false;
+    while (std::fscanf(f, "%d %d %d %d", &w, &h, &k, &v) == 4)
+        if (w == W && h == H && k == K) {
+            *nb = v;
+            found = true;
+        }
+    std::fclose(f);
+    return found;
+}
+}  // namespace
+
+gid_status gid_autotune(gid_ctx* c, const char* cache_path, int32_t* chosen) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    int nb = 0;
+    if (cache_lookup(cache_path, c->W, c->H, c->K, &nb)) {
+        set_nblocks(c, nb);
+        if (chosen) *chosen = c->nblocks;
+        return GID_OK;
+    }
+    // time the stencil kernels of a layer step (single-step forms: no solver state
+    // changes except the scratch vectors q and M^-1) for each candidate grid
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GID_HIP(c, hipEventCreate(&e0));
+    GID_HIP(c, hipEventCreate(&e1));
+    const int cand[] = {64, 128, 256, 384, 512, 768, 1024, 1536, 2048};
+    double best_ms = 1e30;
+    int best = c->nblocks;
+    gid_status status = GID_OK;
+    for (int nbc : cand) {
+        if (nbc > (int)align_up((size_t)c->ntiles, 8) && nbc != cand[0]) continue;
+        set_nblocks(c, nbc);
+        Args a = step_args(c);
+        Step s{};
+        s.debug = 1;
+        a.out = c->q;
+        a.out2 = c->minv;
+        a.pdebug = c->pA;
+        float ms_total = 0.0f;
+        for (int rep = 0; rep < 4; ++rep) {
+            if (hipEventRecord(e0, c->stream) != hipSuccess ||
+                launch_kernel(KN_GN_BUILD, a, s, c->stream) != hipSuccess ||
+                launch_kernel(KN_MATVEC, a, s, c->stream) != hipSuccess ||
+                launch_kernel(KN_MATVEC, a, s, c->stream) != hipSuccess ||
+                hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                status = fail(c, GID_ERR_HIP, "autotune launch failed");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) ms_total += ms;      // the first repetition warms caches
+        }
+        if (status != GID_OK) break;
+        if (ms_total < best_ms) {
+            best_ms = ms_total;
+            best = c->nblocks;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_nblocks(c, best);
+    if (status != GID_OK) return status;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%d %d %d %d\n", c->W, c->H, c->K, c->nblocks);
+            std::fclose(f);
+        }
+    }
+    if (chosen) *chosen = c->nblocks;
+    return GID_OK;
+}
+
+gid_status gid_set_workgroups(gid_ctx* c, int32_t nb) {
+    if (!c || nb < 8 || nb > NB_TUNE_MAX) return GID_ERR_INVALID_ARG;
+    GID_HIP(c, hipStreamSynchronize(c->stream));
+    set_nblocks(c, nb);
+    return GID_OK;
+}
+
+int32_t gid_get_workgroups(const gid_ctx* c) { return c ? c->nblocks : 0; }
 
 const char* gid_status_string(gid_status s) {
     switch (s) {

@@ -41,29 +41,36 @@ struct Lam {
     double gate, cfloor;     // compared in FP64 against FP64 chromaticity distances
 };
 
-// Everything a kernel may touch; passed by value.
+// Fields that change from launch to launch of one schedule.
+struct Step {
+    int iter;       // PCG iteration (matvec, update); apply pass: index of the last one
+    int slot;       // energy log slot
+    int gn;         // Gauss-Newton iteration (log of <r, z>)
+    int refine;     // apply pass: accumulate the base-colour sums
+    int add_delta;  // apply pass: u += delta (0: sums only)
+    int log_rz;     // apply pass: record the final <r, z> of the layer step
+    int debug;      // single-step access: skip scalar bookkeeping / use caller buffers
+};
+
+// One clip: its geometry, parameters and every buffer a kernel may touch.
+// Passed by value to single-clip launches; kept in device memory (one per clip)
+// for batched launches.
 struct Args {
     int W, H, K;
     int ppt;                 // pixel rows per thread (tile height = TYW * ppt)
     int ntx, nty, ntiles;    // tile grid
-    int nblocks;             // launched workgroups (multiple of 8)
+    int nblocks;             // workgroups of a per-pixel launch (multiple of 8)
+    int nb_bs;               // workgroups of the apply + base-colour-sum launch (multiple of 8)
     long long ps;            // plane stride in elements
     Lam lam;
     int temporal;            // consistency prior active for this frame
     int first;               // initialise the unknowns (first frame of a clip)
-    int refine;              // base-colour step active in this GN iteration
     int cr_literal;
-    int iter;                // PCG iteration index (matvec / update)
-    int slot;                // energy log slot
-    int debug;               // single-step access: skip scalar bookkeeping
-    int gn;                  // GN iteration index (rz log)
-    int add_delta;           // apply pass: u += delta (0: sums only)
-    int log_rz;              // apply pass: record the final <r, z> of the layer step
     float* u;                // n planes
     float* delta;
     float* res;
-    float* pold;             // p of the previous PCG iteration
-    float* pnew;             // p of this iteration
+    float* pA;               // search direction, even iterations (and p0)
+    float* pB;               // search direction, odd iterations
     float* q;
     float* minv;
     float* I;                // 3 planes (frame copy)
@@ -74,6 +81,7 @@ struct Args {
     float* rprev;            // 3 planes, previous frame's final r
     float* bf;               // K x 3 base colours, float
     float* lnb;              // K x 3 ln b, float
+    float* bcf;              // K x 3 base colours minus their channel mean, float
     double* b64;             // K x 3 base colours, double (master)
     double* lnb64;           // K x 3 ln b, double
     double* binit64;         // K x 3 initial estimate
@@ -93,17 +101,24 @@ struct Args {
 // Number of base-colour step sums: 3 K(K+1)/2 Gram entries + 3K right-hand side entries.
 __host__ __device__ inline int bstep_nsums(int K) { return 3 * K * (K + 1) / 2 + 3 * K; }
 
-// Launchers (return hipError_t of the launch).
-hipError_t launch_precompute(const Args& a, hipStream_t s);
-hipError_t launch_gn_build(const Args& a, hipStream_t s);
-hipError_t launch_matvec(const Args& a, hipStream_t s);
-hipError_t launch_update(const Args& a, hipStream_t s);
-hipError_t launch_apply_bsum(const Args& a, int nblocks_bs, hipStream_t s);
-hipError_t launch_bsolve(const Args& a, int nblocks_bs, hipStream_t s);
-hipError_t launch_energy(const Args& a, hipStream_t s);
-hipError_t launch_energy_finish(const Args& a, hipStream_t s);
-hipError_t launch_output(const Args& a, hipStream_t s);
-hipError_t launch_reset_frame(const Args& a, hipStream_t s);
-hipError_t launch_scan(const Args& a, hipStream_t s);
+enum Kern : int {
+    KN_RESET = 0, KN_SCAN, KN_PRECOMPUTE, KN_GN_BUILD, KN_MATVEC, KN_UPDATE, KN_APPLY_BSUM, KN_BSOLVE,
+    KN_ENERGY, KN_ENERGY_FINISH, KN_OUTPUT, KN_TABLES
+};
+
+// A batched launch over several clips: per-clip descriptors in device memory and
+// device prefix tables of the per-clip workgroup counts (each a multiple of 8).
+struct BatchGrid {
+    const Args* args;
+    const int* wg_pix;      // per-pixel launches
+    const int* wg_bs;       // apply + base-colour-sum launches
+    int nclips;
+    int total_pix, total_bs;
+    int kb;                 // largest K in the batch (selects the compiled K bucket)
+};
+
+// Launch one kernel for one clip / for a batch (returns the launch error).
+hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s);
+hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t s);
 
 }  // namespace gid

@@ -7,11 +7,16 @@
 // wavefronts; it covers a tile of 64 columns x (4 * ppt) rows, each wavefront one
 // row of 64 pixels, so every plane access is a 256-byte coalesced row segment.
 // Tiles are handed to workgroups XCD-aware: the hardware deals workgroup i to XCD
-// i % 8, and logical_block() gives each XCD a contiguous band of tiles so that
-// the halo rows a tile shares with its vertical neighbours stay in that XCD's L2.
+// i % 8, and xcd_order() gives each XCD a contiguous band of tiles so that the
+// halo rows a tile shares with its vertical neighbours stay in that XCD's L2.
 //
 // Grids are persistent-style: at most a few workgroups per CU, each owning a
 // contiguous chunk of tiles, so a launch produces at most ~1024 partial sums.
+// Every kernel is a body over (clip descriptor, launch context, step); a
+// single-clip launch runs it over its whole grid, a batched launch runs the
+// bodies of several clips of uneven size and K in one grid, each workgroup
+// finding its clip from a prefix table and branching to the body compiled for
+// that clip's K.
 //
 // Precision: unknowns and PCG vectors are FP32; every dot product, alpha, beta,
 // base-colour sum, the 3K x 3K solve and the energy are FP64.  Reductions are
@@ -31,11 +36,17 @@
 namespace gid {
 namespace {
 
-__device__ __forceinline__ int logical_block() {
-    const int per = gridDim.x >> 3;
-    const int b = blockIdx.x;
-    return (b & 7) * per + (b >> 3);
-}
+// Position of a workgroup within its clip's launch: lb is the XCD-aware logical
+// index among the clip's nb workgroups (nb a multiple of 8, and the clip's first
+// workgroup index a multiple of 8, so workgroup lb runs on XCD j % 8 where j is
+// its index within the clip).
+struct Lc {
+    int lb, nb;
+};
+
+__device__ __forceinline__ int xcd_order(int j, int nb) { return (j & 7) * (nb >> 3) + (j >> 3); }
+
+__device__ __forceinline__ Lc whole_grid() { return Lc{xcd_order((int)blockIdx.x, (int)gridDim.x), (int)gridDim.x}; }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -57,9 +68,9 @@ __device__ __forceinline__ double* site_ptr(const Args& a, int site) {
 }
 
 // Store this workgroup's nv values (every thread holds them) as partials of a site.
-__device__ __forceinline__ void publish(const Args& a, int site, const double* vals, int nv) {
+__device__ __forceinline__ void publish(const Args& a, const Lc& lc, int site, const double* vals, int nv) {
     double* p = site_ptr(a, site);
-    if ((int)threadIdx.x < nv) p[(long long)threadIdx.x * gridDim.x + blockIdx.x] = vals[threadIdx.x];
+    if ((int)threadIdx.x < nv) p[(long long)threadIdx.x * lc.nb + lc.lb] = vals[threadIdx.x];
 }
 
 // Total of value v of a site produced by a launch of nb workgroups; every
@@ -77,10 +88,9 @@ __device__ __forceinline__ int rz_site(int i) { return (i & 1) ? R_RZB : R_RZA; 
 
 // Visit every pixel of this workgroup's contiguous chunk of tiles: f(x, y, i).
 template <typename F>
-__device__ __forceinline__ void for_each_pixel(const Args& a, F&& f) {
-    const int lb = logical_block();
-    const int t0 = (int)(((long long)lb * a.ntiles) / gridDim.x);
-    const int t1 = (int)(((long long)(lb + 1) * a.ntiles) / gridDim.x);
+__device__ __forceinline__ void for_each_pixel(const Args& a, const Lc& lc, F&& f) {
+    const int t0 = (int)(((long long)lc.lb * a.ntiles) / lc.nb);
+    const int t1 = (int)(((long long)(lc.lb + 1) * a.ntiles) / lc.nb);
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int rows = TYW * a.ppt;
     for (int tile = t0; tile < t1; ++tile) {
@@ -95,51 +105,34 @@ __device__ __forceinline__ void for_each_pixel(const Args& a, F&& f) {
     }
 }
 
-__device__ __forceinline__ bool lead_thread() { return blockIdx.x == 0 && threadIdx.x == 0; }
+__device__ __forceinline__ bool lead_thread(const Lc& lc) { return lc.lb == 0 && threadIdx.x == 0; }
 
 // Basis with the white illuminant first, and the basis minus its channel mean.
+// Both come from device tables with uniform addresses, so they live in scalar
+// registers (the base-colour solve and the colour upload maintain the tables).
 template <int K>
 struct Basis {
     float B[K + 1][3];
     float Bc[K + 1][3];
-    __device__ __forceinline__ void load(const float* bf) {
+    __device__ __forceinline__ void load(const float* bf, const float* bcf) {
         B[0][0] = B[0][1] = B[0][2] = 1.0f;
         Bc[0][0] = Bc[0][1] = Bc[0][2] = 0.0f;
 #pragma unroll
         for (int k = 1; k <= K; ++k) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) B[k][c] = bf[(k - 1) * 3 + c];
-            const float mu = (B[k][0] + B[k][1] + B[k][2]) * (1.0f / 3.0f);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Bc[k][c] = B[k][c] - mu;
+            for (int c = 0; c < 3; ++c) {
+                B[k][c] = bf[(k - 1) * 3 + c];
+                Bc[k][c] = bcf[(k - 1) * 3 + c];
+            }
         }
     }
 };
 
-// IRLS weight of the reflectance-gradient sparsity term at a pixel from its
-// forward differences (the norm over both directions and all channels).
-__device__ __forceinline__ float w_rsparsity(const float* r0, bool hr, const float* rr, bool hd,
-                                             const float* rd, const Lam& L) {
-    float s = 0.0f;
-    if (hr) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float d = rr[c] - r0[c];
-            s += d * d;
-        }
-    }
-    if (hd) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float d = rd[c] - r0[c];
-            s += d * d;
-        }
-    }
-    const float nrm = sqrtf(s) + L.eps_irls;
-    return (L.p == 1.0f) ? 1.0f / nrm : powf(nrm, L.p - 2.0f);
-}
+// Reciprocal of an IRLS denominator |x| + eps (always >= eps > 0): the hardware
+// reciprocal, within 1 ulp.
+__device__ __forceinline__ float rcp_pos(float x) { return __builtin_amdgcn_rcpf(x); }
 
-__device__ __forceinline__ float w_pair(float a, float b, float eps) { return 1.0f / (fabsf(b - a) + eps); }
+__device__ __forceinline__ float w_pair(float a, float b, float eps) { return rcp_pos(fabsf(b - a) + eps); }
 
 __device__ __forceinline__ void load3(const float* base, long long ps, long long i, float* v) {
     v[0] = base[i];
@@ -147,65 +140,35 @@ __device__ __forceinline__ void load3(const float* base, long long ps, long long
     v[2] = base[2 * ps + i];
 }
 
-// Lambda-scaled weights of the four reflectance-gradient pairs touching pixel
-// (x, y): right and down use the pixel's own weight, left and up the weights of
-// the left and upper neighbours.  Zero where the pair does not exist.
-__device__ __forceinline__ void rsparsity_pairs(const Args& a, int x, int y, long long i, float wr[4]) {
-    const long long ps = a.ps;
-    const int W = a.W, H = a.H;
-    const bool hr = x + 1 < W, hd = y + 1 < H, hl = x > 0, hu = y > 0;
-    float r0[3], rr[3] = {0, 0, 0}, rd[3] = {0, 0, 0}, rl[3] = {0, 0, 0}, ru[3] = {0, 0, 0};
-    load3(a.u, ps, i, r0);
-    if (hr) load3(a.u, ps, i + 1, rr);
-    if (hd) load3(a.u, ps, i + W, rd);
-    if (hl) load3(a.u, ps, i - 1, rl);
-    if (hu) load3(a.u, ps, i - W, ru);
-    const float lr = a.lam.rs;
-    const float wself = (hr || hd) ? lr * w_rsparsity(r0, hr, rr, hd, rd, a.lam) : 0.0f;
-    wr[0] = hr ? wself : 0.0f;
-    wr[1] = hd ? wself : 0.0f;
-    if (hl) {
-        float rld[3] = {0, 0, 0};
-        const bool ld = y + 1 < H;
-        if (ld) load3(a.u, ps, i - 1 + W, rld);
-        wr[2] = lr * w_rsparsity(rl, true, r0, ld, rld, a.lam);
-    } else {
-        wr[2] = 0.0f;
-    }
-    if (hu) {
-        float rur[3] = {0, 0, 0};
-        const bool ur = x + 1 < W;
-        if (ur) load3(a.u, ps, i - W + 1, rur);
-        wr[3] = lr * w_rsparsity(ru, ur, rur, true, r0, a.lam);
-    } else {
-        wr[3] = 0.0f;
-    }
-}
+// Search-direction buffers: iteration i writes p into p_new(i); its predecessor
+// is p_old(i) (the build writes p0 into pA).
+__device__ __forceinline__ float* p_new(const Args& a, int i) { return (i & 1) ? a.pB : a.pA; }
+__device__ __forceinline__ float* p_old(const Args& a, int i) { return (i == 0 || !((i - 1) & 1)) ? a.pA : a.pB; }
 
 // p of the current PCG iteration at plane element j: the stored p0 for the first
 // iteration, z + beta p_old afterwards (recomputed identically by every reader).
-__device__ __forceinline__ float p_at(const Args& a, long long j, double beta) {
-    if (a.iter == 0) return a.pold[j];
+__device__ __forceinline__ float p_at(const Args& a, const float* pold, bool first, long long j, double beta) {
+    if (first) return pold[j];
     const float z = a.res[j] * a.minv[j];
-    return (float)((double)z + beta * (double)a.pold[j]);
+    return (float)((double)z + beta * (double)pold[j]);
 }
 
 // --------------------------------------------------------------- input scan
 
 // Count non-finite frame values and cluster ids outside [0, K); any hit makes the
 // rest of the frame's kernels no-ops so the solver state is left unchanged.
-__global__ __launch_bounds__(NTHREADS) void k_scan(Args a) {
-    __shared__ double sh4[4];
+__device__ __forceinline__ void scan_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+    double* sh4 = reinterpret_cast<double*>(smem);
     const long long ps = a.ps;
     double bad = 0.0;
-    for_each_pixel(a, [&](int x, int y, long long i) {
+    for_each_pixel(a, lc, [&](int x, int y, long long i) {
         float v[3];
         load3(a.in_frame, ps, i, v);
         if (!isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2])) bad += 1.0;
         if ((int)a.in_ids[i] >= a.K) bad += 1.0;
     });
     const double vals[1] = {block_sum(bad, sh4)};
-    publish(a, R_SCAN, vals, 1);
+    publish(a, lc, R_SCAN, vals, 1);
 }
 
 // ----------------------------------------------------------------- precompute
@@ -228,17 +191,17 @@ __device__ __forceinline__ double cdist(const double* a, const double* b) {
 }
 
 template <int K>
-__global__ __launch_bounds__(NTHREADS) void k_precompute(Args a) {
-    __shared__ double sh4[4];
+__device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+    double* sh4 = reinterpret_cast<double*>(smem);
     // input check of the scan (every workgroup computes the same total)
-    const double bad = site_total(a, R_SCAN, 0, gridDim.x, sh4);
-    if (lead_thread()) a.scal[S_BADIN] = bad;
+    const double bad = site_total(a, R_SCAN, 0, lc.nb, sh4);
+    if (lead_thread(lc)) a.scal[S_BADIN] = bad;
     if (bad != 0.0) return;
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
     const double floor_ = a.lam.cfloor;
     const float* F = a.in_frame;
-    for_each_pixel(a, [&](int x, int y, long long i) {
+    for_each_pixel(a, lc, [&](int x, int y, long long i) {
         float Iv[3];
         load3(F, ps, i, Iv);
         a.I[i] = Iv[0];
@@ -291,310 +254,414 @@ __global__ __launch_bounds__(NTHREADS) void k_precompute(Args a) {
     });
 }
 
+// ------------------------------------------------------- halo-staged tiles
+
+// The stencil kernels (GN build, matvec) stage a 66 x 6 halo'd tile of every
+// plane they read into LDS with one load phase, then read neighbours from LDS.
+constexpr int HW = TX + 2;          // halo'd tile width
+constexpr int HH = TYW + 2;         // halo'd tile height (tiles of 64 x 4 pixels)
+constexpr int HN = HW * HH;
+
+__device__ __forceinline__ void chunk_of(const Args& a, const Lc& lc, int& t0, int& t1) {
+    t0 = (int)(((long long)lc.lb * a.ntiles) / lc.nb);
+    t1 = (int)(((long long)(lc.lb + 1) * a.ntiles) / lc.nb);
+}
+
+// IRLS weight of the reflectance-gradient term at halo'd-tile index li, from
+// the forward differences that exist (the norm over both directions and all
+// channels).  Ul holds the three r planes.
+__device__ __forceinline__ float w_rs_lds(const float* Ul, int li, bool hr, bool hd, const Lam& L) {
+    float s = 0.0f;
+    if (hr) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float d = Ul[c * HN + li + 1] - Ul[c * HN + li];
+            s += d * d;
+        }
+    }
+    if (hd) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float d = Ul[c * HN + li + HW] - Ul[c * HN + li];
+            s += d * d;
+        }
+    }
+    const float nrm = sqrtf(s) + L.eps_irls;
+    return (L.p == 1.0f) ? rcp_pos(nrm) : powf(nrm, L.p - 2.0f);
+}
+
+// Lambda-scaled weights of the four reflectance-gradient pairs touching the
+// pixel (right, down, left, up); zero where the pair does not exist.
+__device__ __forceinline__ void rs_pairs_lds(const Args& a, const float* Ul, int li, int x, int y, float wr[4]) {
+    const int W = a.W, H = a.H;
+    const bool hr = x + 1 < W, hd = y + 1 < H, hl = x > 0, hu = y > 0;
+    const float lr = a.lam.rs;
+    const float ws = (hr || hd) ? lr * w_rs_lds(Ul, li, hr, hd, a.lam) : 0.0f;
+    wr[0] = hr ? ws : 0.0f;
+    wr[1] = hd ? ws : 0.0f;
+    wr[2] = hl ? lr * w_rs_lds(Ul, li - 1, true, hd, a.lam) : 0.0f;
+    wr[3] = hu ? lr * w_rs_lds(Ul, li - HW, hr, true, a.lam) : 0.0f;
+}
+
 // ------------------------------------------------------------------ GN build
 
 template <int K>
-__global__ __launch_bounds__(NTHREADS) void k_gn_build(Args a) {
+__device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
-    __shared__ double sh4[4];
+    double* sh4 = reinterpret_cast<double*>(smem);
+    float* Ul = reinterpret_cast<float*>(smem + 32);
     if (a.scal[S_BADIN] != 0.0) return;
     Basis<K> bs;
-    bs.load(a.bf);
+    bs.load(a.bf, a.bcf);
     const Lam L = a.lam;
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int li = (ly + 1) * HW + lx + 1;
+    const int off[4] = {1, HW, -1, -HW};
+    int t0, t1;
+    chunk_of(a, lc, t0, t1);
     double acc = 0.0;
-    for_each_pixel(a, [&](int x, int y, long long i) {
-        float r[3], T[K + 1], Iv[3];
-        load3(a.u, ps, i, r);
-#pragma unroll
-        for (int k = 0; k <= K; ++k) T[k] = a.u[(3 + k) * ps + i];
-        load3(a.I, ps, i, Iv);
-        const int id = a.ids[i];
-        const float w = a.wsr[i];
-        float R[3], S[3], e[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            R[c] = expf(r[c]);
-            float s = 0.0f;
-#pragma unroll
-            for (int k = 0; k <= K; ++k) s += bs.B[k][c] * T[k];
-            S[c] = s;
-            e[c] = Iv[c] - R[c] * s;
+    for (int tile = t0; tile < t1; ++tile) {
+        const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TYW;
+        for (int idx = threadIdx.x; idx < HN; idx += NTHREADS) {
+            const int gx = x0 + idx % HW - 1, gy = y0 + idx / HW - 1;
+            const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+            const long long gi = (long long)gy * W + gx;
+#pragma unroll 4
+            for (int v = 0; v < N; ++v) Ul[v * HN + idx] = in ? a.u[v * ps + gi] : 0.0f;
         }
-        float g[N], M[N];
-        const float gs = a.temporal ? a.tg[i] : 0.0f;
+        __syncthreads();
+        const int x = x0 + lx, y = y0 + ly;
+        if (x < W && y < H) {
+            const long long i = (long long)y * W + x;
+            const bool hv[4] = {x + 1 < W, y + 1 < H, x > 0, y > 0};
+            float r[3], T[K + 1], Iv[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float RS = R[c] * S[c];
-            const float tgr = a.temporal ? a.tg[(1 + c) * ps + i] : 0.0f;
-            g[c] = L.data * RS * e[c] - L.cl * (r[c] - a.lnb[3 * id + c]) - L.rc * (gs * r[c] - tgr);
-            M[c] = L.data * RS * RS + L.cl + L.rc * gs;
-        }
-        const float mS = (S[0] + S[1] + S[2]) * (1.0f / 3.0f);
-        float md[3];
+            for (int c = 0; c < 3; ++c) r[c] = Ul[c * HN + li];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) md[c] = S[c] - mS;
-#pragma unroll
-        for (int k = 0; k <= K; ++k) {
-            float gd = 0.0f, Md = 0.0f, gm = 0.0f, Mm = 0.0f;
+            for (int k = 0; k <= K; ++k) T[k] = Ul[(3 + k) * HN + li];
+            load3(a.I, ps, i, Iv);
+            const int id = a.ids[i];
+            const float w = a.wsr[i];
+            float R[3], S[3], e[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float RB = R[c] * bs.B[k][c];
-                gd += RB * e[c];
-                Md += RB * RB;
-                gm += bs.Bc[k][c] * md[c];
-                Mm += bs.Bc[k][c] * bs.Bc[k][c];
+                R[c] = expf(r[c]);
+                float sum = 0.0f;
+#pragma unroll
+                for (int k = 0; k <= K; ++k) sum += bs.B[k][c] * T[k];
+                S[c] = sum;
+                e[c] = Iv[c] - R[c] * sum;
             }
-            const float at = fabsf(T[k]);
-            const float wis = (k > 0) ? L.is / (at + L.eps_irls) : 0.0f;
-            const float wnn = (T[k] > 0.0f) ? 0.0f : L.nn / (at + L.eps_nn);
-            g[3 + k] = L.data * gd - L.mo * w * gm - (wis + wnn) * T[k];
-            M[3 + k] = L.data * Md + L.mo * w * Mm + wis + wnn;
-        }
-        // reflectance sparsity stencil
-        {
-            float wr[4];
-            rsparsity_pairs(a, x, y, i, wr);
-            const long long nb[4] = {i + 1, i + W, i - 1, i - W};
+            float g[N], M[N];
+            const float gs = a.temporal ? a.tg[i] : 0.0f;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                if (wr[d] == 0.0f) continue;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) g[c] -= wr[d] * (r[c] - a.u[c * ps + nb[d]]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) M[c] += wr[d];
+            for (int c = 0; c < 3; ++c) {
+                const float RS = R[c] * S[c];
+                const float tgr = a.temporal ? a.tg[(1 + c) * ps + i] : 0.0f;
+                g[c] = L.data * RS * e[c] - L.cl * (r[c] - a.lnb[3 * id + c]) - L.rc * (gs * r[c] - tgr);
+                M[c] = L.data * RS * RS + L.cl + L.rc * gs;
             }
-        }
-        // smoothness stencil, one layer at a time
-        {
-            const bool hv[4] = {x + 1 < W, y + 1 < H, x > 0, y > 0};
-            const long long nb[4] = {i + 1, i + W, i - 1, i - W};
+            const float mS = (S[0] + S[1] + S[2]) * (1.0f / 3.0f);
+            float md[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) md[c] = S[c] - mS;
 #pragma unroll
             for (int k = 0; k <= K; ++k) {
-                const float* Tk = a.u + (3 + k) * ps;
+                float gd = 0.0f, Md = 0.0f, gm = 0.0f, Mm = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float RB = R[c] * bs.B[k][c];
+                    gd += RB * e[c];
+                    Md += RB * RB;
+                    gm += bs.Bc[k][c] * md[c];
+                    Mm += bs.Bc[k][c] * bs.Bc[k][c];
+                }
+                const float at = fabsf(T[k]);
+                const float wis = (k > 0) ? L.is * rcp_pos(at + L.eps_irls) : 0.0f;
+                const float wnn = (T[k] > 0.0f) ? 0.0f : L.nn * rcp_pos(at + L.eps_nn);
+                g[3 + k] = L.data * gd - L.mo * w * gm - (wis + wnn) * T[k];
+                M[3 + k] = L.data * Md + L.mo * w * Mm + wis + wnn;
+            }
+            // reflectance sparsity stencil
+            float wr[4];
+            rs_pairs_lds(a, Ul, li, x, y, wr);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    g[c] -= wr[d] * (r[c] - Ul[c * HN + li + off[d]]);
+                    M[c] += wr[d];
+                }
+            }
+            // smoothness stencil
+#pragma unroll
+            for (int k = 0; k <= K; ++k) {
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
                     if (!hv[d]) continue;
-                    const float tn = Tk[nb[d]];
+                    const float tn = Ul[(3 + k) * HN + li + off[d]];
                     const float ws = L.sm * w_pair(T[k], tn, L.eps_irls);
                     g[3 + k] -= ws * (T[k] - tn);
                     M[3 + k] += ws;
                 }
             }
-        }
-        if (a.debug) {
+            if (st.debug) {
 #pragma unroll
-            for (int v = 0; v < N; ++v) {
-                a.out[v * ps + i] = g[v];
-                a.out2[v * ps + i] = M[v];
-            }
-        } else {
+                for (int v = 0; v < N; ++v) {
+                    a.out[v * ps + i] = g[v];
+                    a.out2[v * ps + i] = M[v];
+                }
+            } else {
 #pragma unroll
-            for (int v = 0; v < N; ++v) {
-                const float mi = 1.0f / M[v];
-                const float z = g[v] * mi;
-                a.res[v * ps + i] = g[v];
-                a.minv[v * ps + i] = mi;
-                a.pnew[v * ps + i] = z;
-                a.delta[v * ps + i] = 0.0f;
-                acc += (double)g[v] * (double)z;
+                for (int v = 0; v < N; ++v) {
+                    const float mi = 1.0f / M[v];
+                    const float z = g[v] * mi;
+                    a.res[v * ps + i] = g[v];
+                    a.minv[v * ps + i] = mi;
+                    a.pA[v * ps + i] = z;
+                    a.delta[v * ps + i] = 0.0f;
+                    acc += (double)g[v] * (double)z;
+                }
             }
         }
-    });
-    if (a.debug) return;
+        __syncthreads();
+    }
+    if (st.debug) return;
     const double vals[1] = {block_sum(acc, sh4)};
-    publish(a, rz_site(-1), vals, 1);
-    if (lead_thread()) a.scal[S_STOP] = 0.0;
+    publish(a, lc, rz_site(-1), vals, 1);
+    if (lead_thread(lc)) a.scal[S_STOP] = 0.0;
 }
 
 // ---------------------------------------------------------------- PCG matvec
 
 template <int K>
-__global__ __launch_bounds__(NTHREADS) void k_matvec(Args a) {
+__device__ __forceinline__ void matvec_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
-    __shared__ double sh4[4];
-    if (!a.debug && (a.scal[S_STOP] != 0.0 || a.scal[S_BADIN] != 0.0)) return;   // uniform over the grid
-    Basis<K> bs;
-    bs.load(a.bf);
-    const Lam L = a.lam;
-    const long long ps = a.ps;
-    const int W = a.W, H = a.H;
+    double* sh4 = reinterpret_cast<double*>(smem);
+    float* Ul = reinterpret_cast<float*>(smem + 32);   // unknowns (r planes, then T planes)
+    float* Pl = Ul + N * HN;                           // search direction p of this iteration
+    if (!st.debug && (a.scal[S_STOP] != 0.0 || a.scal[S_BADIN] != 0.0)) return;   // uniform over the grid
     double beta = 0.0;
-    if (!a.debug && a.iter > 0) {
+    if (!st.debug && st.iter > 0) {
         // beta of the previous iteration from the last two <r, z> totals
-        const double rz_now = site_total(a, rz_site(a.iter - 1), 0, gridDim.x, sh4);
-        const double rz_before = site_total(a, rz_site(a.iter - 2), 0, gridDim.x, sh4);
-        if (lead_thread()) a.scal[S_RZ_LOG + (a.gn & 63)] = rz_now;
+        const double rz_now = site_total(a, rz_site(st.iter - 1), 0, lc.nb, sh4);
+        const double rz_before = site_total(a, rz_site(st.iter - 2), 0, lc.nb, sh4);
+        if (lead_thread(lc)) a.scal[S_RZ_LOG + (st.gn & 63)] = rz_now;
         if (rz_now == 0.0) {      // converged exactly: the rest of the layer step is a no-op
-            if (lead_thread()) a.scal[S_STOP] = 1.0;
+            if (lead_thread(lc)) a.scal[S_STOP] = 1.0;
             return;
         }
         beta = rz_now / rz_before;
     }
-    Args ad = a;
-    if (a.debug) {               // apply J^T J to a caller vector
-        ad.iter = 0;
-        ad.pold = const_cast<float*>(a.pdebug);
-    }
+    // single-step access applies J^T J to a caller vector
+    const bool pfirst = st.debug || st.iter == 0;
+    const float* pold = st.debug ? a.pdebug : p_old(a, st.iter);
+    float* pnw = p_new(a, st.iter);
+    Basis<K> bs;
+    bs.load(a.bf, a.bcf);
+    const Lam L = a.lam;
+    const long long ps = a.ps;
+    const int W = a.W, H = a.H;
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int li = (ly + 1) * HW + lx + 1;
+    const int off[4] = {1, HW, -1, -HW};
+    int t0, t1;
+    chunk_of(a, lc, t0, t1);
     double acc = 0.0;
-    for_each_pixel(a, [&](int x, int y, long long i) {
-        float p[N], q[N];
-#pragma unroll
-        for (int v = 0; v < N; ++v) p[v] = p_at(ad, v * ps + i, beta);
-        float r[3], T[K + 1];
-        load3(a.u, ps, i, r);
-#pragma unroll
-        for (int k = 0; k <= K; ++k) T[k] = a.u[(3 + k) * ps + i];
-        float R[3], S[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            R[c] = expf(r[c]);
-            float s = 0.0f;
-#pragma unroll
-            for (int k = 0; k <= K; ++k) s += bs.B[k][c] * T[k];
-            S[c] = s;
+    for (int tile = t0; tile < t1; ++tile) {
+        const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TYW;
+        for (int idx = threadIdx.x; idx < HN; idx += NTHREADS) {
+            const int gx = x0 + idx % HW - 1, gy = y0 + idx / HW - 1;
+            const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
+            const long long gi = (long long)gy * W + gx;
+#pragma unroll 2
+            for (int v = 0; v < N; ++v) {
+                Ul[v * HN + idx] = in ? a.u[v * ps + gi] : 0.0f;
+                Pl[v * HN + idx] = in ? p_at(a, pold, pfirst, v * ps + gi, beta) : 0.0f;
+            }
         }
-        // data term block
-        float ac[3];
+        __syncthreads();
+        const int x = x0 + lx, y = y0 + ly;
+        if (x < W && y < H) {
+            const long long i = (long long)y * W + x;
+            const bool hv[4] = {x + 1 < W, y + 1 < H, x > 0, y > 0};
+            float p[N], q[N], T[K + 1], R[3], S[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float s = S[c] * p[c];
+            for (int v = 0; v < N; ++v) p[v] = Pl[v * HN + li];
 #pragma unroll
-            for (int k = 0; k <= K; ++k) s += bs.B[k][c] * p[3 + k];
-            ac[c] = R[c] * s;
-        }
-        const float gs = a.temporal ? a.tg[i] : 0.0f;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) q[c] = L.data * R[c] * S[c] * ac[c] + (L.cl + L.rc * gs) * p[c];
-        // monochrome block
-        const float w = a.wsr[i];
-        float m[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float s = 0.0f;
-#pragma unroll
-            for (int k = 1; k <= K; ++k) s += bs.Bc[k][c] * p[3 + k];
-            m[c] = s;
-        }
-#pragma unroll
-        for (int k = 0; k <= K; ++k) {
-            float sd = 0.0f, sm = 0.0f;
+            for (int k = 0; k <= K; ++k) T[k] = Ul[(3 + k) * HN + li];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                sd += R[c] * bs.B[k][c] * ac[c];
-                sm += bs.Bc[k][c] * m[c];
-            }
-            const float at = fabsf(T[k]);
-            const float wis = (k > 0) ? L.is / (at + L.eps_irls) : 0.0f;
-            const float wnn = (T[k] > 0.0f) ? 0.0f : L.nn / (at + L.eps_nn);
-            q[3 + k] = L.data * sd + L.mo * w * sm + (wis + wnn) * p[3 + k];
-        }
-        // reflectance sparsity stencil
-        {
-            float wr[4];
-            rsparsity_pairs(a, x, y, i, wr);
-            const long long nb[4] = {i + 1, i + W, i - 1, i - W};
+                R[c] = expf(Ul[c * HN + li]);
+                float sum = 0.0f;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                if (wr[d] == 0.0f) continue;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) q[c] += wr[d] * (p[c] - p_at(ad, c * ps + nb[d], beta));
+                for (int k = 0; k <= K; ++k) sum += bs.B[k][c] * T[k];
+                S[c] = sum;
             }
-        }
-        // smoothness stencil
-        {
-            const bool hv[4] = {x + 1 < W, y + 1 < H, x > 0, y > 0};
-            const long long nb[4] = {i + 1, i + W, i - 1, i - W};
+            // data term block
+            float ac[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float sum = S[c] * p[c];
+#pragma unroll
+                for (int k = 0; k <= K; ++k) sum += bs.B[k][c] * p[3 + k];
+                ac[c] = R[c] * sum;
+            }
+            const float gs = a.temporal ? a.tg[i] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) q[c] = L.data * R[c] * S[c] * ac[c] + (L.cl + L.rc * gs) * p[c];
+            // monochrome block and unary layer terms
+            const float w = a.wsr[i];
+            float m[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float sum = 0.0f;
+#pragma unroll
+                for (int k = 1; k <= K; ++k) sum += bs.Bc[k][c] * p[3 + k];
+                m[c] = sum;
+            }
 #pragma unroll
             for (int k = 0; k <= K; ++k) {
-                const float* Tk = a.u + (3 + k) * ps;
+                float sd = 0.0f, sm = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    sd += R[c] * bs.B[k][c] * ac[c];
+                    sm += bs.Bc[k][c] * m[c];
+                }
+                const float at = fabsf(T[k]);
+                const float wis = (k > 0) ? L.is * rcp_pos(at + L.eps_irls) : 0.0f;
+                const float wnn = (T[k] > 0.0f) ? 0.0f : L.nn * rcp_pos(at + L.eps_nn);
+                q[3 + k] = L.data * sd + L.mo * w * sm + (wis + wnn) * p[3 + k];
+            }
+            // reflectance sparsity stencil
+            float wr[4];
+            rs_pairs_lds(a, Ul, li, x, y, wr);
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) q[c] += wr[d] * (p[c] - Pl[c * HN + li + off[d]]);
+            // smoothness stencil (one layer at a time: unrolling it makes the
+            // compiler hoist every layer's LDS reads and double the registers)
+#pragma unroll 1
+            for (int k = 0; k <= K; ++k) {
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
                     if (!hv[d]) continue;
-                    const float ws = L.sm * w_pair(T[k], Tk[nb[d]], L.eps_irls);
-                    q[3 + k] += ws * (p[3 + k] - p_at(ad, (3 + k) * ps + nb[d], beta));
+                    const float ws = L.sm * w_pair(T[k], Ul[(3 + k) * HN + li + off[d]], L.eps_irls);
+                    q[3 + k] += ws * (p[3 + k] - Pl[(3 + k) * HN + li + off[d]]);
+                }
+            }
+            if (st.debug) {
+#pragma unroll
+                for (int v = 0; v < N; ++v) a.out[v * ps + i] = q[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    a.q[v * ps + i] = q[v];
+                    if (st.iter > 0) pnw[v * ps + i] = p[v];
+                    acc += (double)p[v] * (double)q[v];
                 }
             }
         }
-        if (a.debug) {
-#pragma unroll
-            for (int v = 0; v < N; ++v) a.out[v * ps + i] = q[v];
-        } else {
-#pragma unroll
-            for (int v = 0; v < N; ++v) {
-                a.q[v * ps + i] = q[v];
-                if (a.iter > 0) a.pnew[v * ps + i] = p[v];
-                acc += (double)p[v] * (double)q[v];
-            }
-        }
-    });
-    if (a.debug) return;
+        __syncthreads();
+    }
+    if (st.debug) return;
     const double vals[1] = {block_sum(acc, sh4)};
-    publish(a, R_PQ, vals, 1);
+    publish(a, lc, R_PQ, vals, 1);
 }
 
 // ---------------------------------------------------------------- PCG update
 
+// Element-wise over the n contiguous planes of each vector, four elements per
+// thread per step: delta += alpha p, r -= alpha q, and the partial <r, M^-1 r>.
 template <int K>
-__global__ __launch_bounds__(NTHREADS) void k_update(Args a) {
+__device__ __forceinline__ void update_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
-    __shared__ double sh4[4];
+    double* sh4 = reinterpret_cast<double*>(smem);
     if (a.scal[S_STOP] != 0.0 || a.scal[S_BADIN] != 0.0) return;
-    const long long ps = a.ps;
-    const double pq = site_total(a, R_PQ, 0, gridDim.x, sh4);
-    const double rz = site_total(a, rz_site(a.iter - 1), 0, gridDim.x, sh4);
+    const double pq = site_total(a, R_PQ, 0, lc.nb, sh4);
+    const double rz = site_total(a, rz_site(st.iter - 1), 0, lc.nb, sh4);
     if (!(pq > 0.0) || !isfinite(pq)) {       // breakdown guard: no update, layer step ends
-        if (lead_thread()) {
+        if (lead_thread(lc)) {
             a.scal[S_STOP] = 1.0;
             a.scal[S_BREAKDOWNS] += 1.0;
-            a.scal[S_RZ_LOG + (a.gn & 63)] = rz;
+            a.scal[S_RZ_LOG + (st.gn & 63)] = rz;
         }
         return;
     }
     const double alpha = rz / pq;
+    const long long total = (long long)N * a.ps;
+    const long long nvec = total / 4;
+    // contiguous element range of this workgroup (in float4 units), XCD-aware order
+    const int lb = lc.lb;
+    const long long v0 = (nvec * lb) / lc.nb, v1 = (nvec * (lb + 1)) / lc.nb;
     double acc = 0.0;
-    for_each_pixel(a, [&](int x, int y, long long i) {
-#pragma unroll
-        for (int v = 0; v < N; ++v) {
-            const long long e = v * ps + i;
-            const float p = a.pnew[e];
-            const float dn = (float)((double)a.delta[e] + alpha * (double)p);
+    float* pcur = p_new(a, st.iter);
+    const float4* P4 = reinterpret_cast<const float4*>(pcur);
+    const float4* Q4 = reinterpret_cast<const float4*>(a.q);
+    const float4* M4 = reinterpret_cast<const float4*>(a.minv);
+    float4* D4 = reinterpret_cast<float4*>(a.delta);
+    float4* R4 = reinterpret_cast<float4*>(a.res);
+    for (long long j = v0 + threadIdx.x; j < v1; j += NTHREADS) {
+        const float4 p = P4[j], q = Q4[j], mi = M4[j];
+        float4 d = D4[j], r = R4[j];
+        d.x = (float)((double)d.x + alpha * (double)p.x);
+        d.y = (float)((double)d.y + alpha * (double)p.y);
+        d.z = (float)((double)d.z + alpha * (double)p.z);
+        d.w = (float)((double)d.w + alpha * (double)p.w);
+        r.x = (float)((double)r.x - alpha * (double)q.x);
+        r.y = (float)((double)r.y - alpha * (double)q.y);
+        r.z = (float)((double)r.z - alpha * (double)q.z);
+        r.w = (float)((double)r.w - alpha * (double)q.w);
+        D4[j] = d;
+        R4[j] = r;
+        acc += (double)r.x * (double)(r.x * mi.x) + (double)r.y * (double)(r.y * mi.y) +
+               (double)r.z * (double)(r.z * mi.z) + (double)r.w * (double)(r.w * mi.w);
+    }
+    // tail elements (total not a multiple of 4), handled by the last workgroup
+    if (lb == lc.nb - 1) {
+        for (long long e = nvec * 4 + threadIdx.x; e < total; e += NTHREADS) {
+            const float dn = (float)((double)a.delta[e] + alpha * (double)pcur[e]);
             const float rn = (float)((double)a.res[e] - alpha * (double)a.q[e]);
             a.delta[e] = dn;
             a.res[e] = rn;
             acc += (double)rn * (double)(rn * a.minv[e]);
         }
-    });
+    }
     const double vals[1] = {block_sum(acc, sh4)};
-    publish(a, rz_site(a.iter), vals, 1);
+    publish(a, lc, rz_site(st.iter), vals, 1);
 }
 
 // ---------------------------------------------------- apply + base-colour sums
 
-constexpr int BS_BATCH = 128;   // pixels staged in LDS per round
+constexpr int BS_BATCH = NTHREADS;   // pixels staged in LDS per round (one per thread)
 
 template <int K>
-__global__ __launch_bounds__(NTHREADS) void k_apply_bsum(Args a) {
+__device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
-    constexpr int NV = 3 * (K + 1);                  // per pixel: R_c T_k (k = 1..K) and R_c e_c
     constexpr int GS = (3 * K <= 32) ? 32 : 64;      // threads per pixel group
     constexpr int NG = NTHREADS / GS;
-    __shared__ double stage[BS_BATCH * NV];
-    __shared__ double red[NG * 3 * K * (K + 1)];
-    __shared__ double sh4[4];
+    // per staged pixel: R_c and the data residual e_c in FP64, T_k (k >= 1) in FP32
+    double* sh4 = reinterpret_cast<double*>(smem);
+    double (*Rs)[BS_BATCH] = reinterpret_cast<double (*)[BS_BATCH]>(smem + 32);
+    double (*Es)[BS_BATCH] = reinterpret_cast<double (*)[BS_BATCH]>(smem + 32 + 3 * BS_BATCH * 8);
+    double* red = reinterpret_cast<double*>(smem + 32 + 6 * BS_BATCH * 8);
+    float (*Ts)[BS_BATCH] = reinterpret_cast<float (*)[BS_BATCH]>(smem + 32 + 6 * BS_BATCH * 8 +
+                                                                    NG * 3 * K * (K + 1) * 8);
     if (a.scal[S_BADIN] != 0.0) return;
-    if (a.log_rz && a.scal[S_STOP] == 0.0) {
+    if (st.log_rz && a.scal[S_STOP] == 0.0) {
         // <r, z> after the last PCG iteration (site of iteration pcg_iters - 1)
-        const double rz = site_total(a, rz_site(a.iter), 0, a.nblocks, sh4);
-        if (lead_thread()) a.scal[S_RZ_LOG + (a.gn & 63)] = rz;
+        const double rz = site_total(a, rz_site(st.iter), 0, a.nblocks, sh4);
+        if (lead_thread(lc)) a.scal[S_RZ_LOG + (st.gn & 63)] = rz;
     }
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
     // this workgroup's contiguous chunk of tiles (XCD-aware)
-    const int lb = logical_block();
-    const int t0 = (int)(((long long)lb * a.ntiles) / gridDim.x);
-    const int t1 = (int)(((long long)(lb + 1) * a.ntiles) / gridDim.x);
+    const int lb = lc.lb;
+    const int t0 = (int)(((long long)lb * a.ntiles) / lc.nb);
+    const int t1 = (int)(((long long)(lb + 1) * a.ntiles) / lc.nb);
     const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
     const bool owner = lane < 3 * K;
     const int oc = owner ? lane / K : 0, ok = owner ? lane % K : 0;
@@ -602,94 +669,112 @@ __global__ __launch_bounds__(NTHREADS) void k_apply_bsum(Args a) {
 #pragma unroll
     for (int l = 0; l <= K; ++l) acc[l] = 0.0;
     double B64[K][3];
-    if (a.refine) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) B64[k][c] = a.b64[3 * k + c];
-    }
+        for (int c = 0; c < 3; ++c) B64[k][c] = st.refine ? a.b64[3 * k + c] : 0.0;
     const int rows = TYW * a.ppt;
     const int tile_px = TX * rows;
     for (int tile = t0; tile < t1; ++tile) {
         const int tx = tile % a.ntx, ty = tile / a.ntx;
         for (int base = 0; base < tile_px; base += BS_BATCH) {
-            // stage: threads 0..BS_BATCH-1 each own one pixel of the batch
-            if (threadIdx.x < BS_BATCH) {
-                const int lp = base + threadIdx.x;
-                const int x = tx * TX + (lp % TX), y = ty * rows + lp / TX;
-                double* sv = stage + threadIdx.x * NV;
-                if (x < W && y < H) {
-                    const long long i = (long long)y * W + x;
-                    float uv[N];
+            // stage: every thread owns one pixel of the batch
+            const int lp = base + threadIdx.x;
+            const int x = tx * TX + (lp % TX), y = ty * rows + lp / TX;
+            const int sp = threadIdx.x;
+            if (x < W && y < H) {
+                const long long i = (long long)y * W + x;
+                float uv[N];
 #pragma unroll
-                    for (int v = 0; v < N; ++v) {
-                        const long long e = v * ps + i;
-                        if (a.add_delta) {
-                            uv[v] = a.u[e] + a.delta[e];
-                            a.u[e] = uv[v];
-                        } else {
-                            uv[v] = a.u[e];
-                        }
+                for (int v = 0; v < N; ++v) {
+                    const long long e = v * ps + i;
+                    if (st.add_delta) {
+                        uv[v] = a.u[e] + a.delta[e];
+                        a.u[e] = uv[v];
+                    } else {
+                        uv[v] = a.u[e];
                     }
-                    if (a.refine) {
-                        double R[3], S[3];
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            R[c] = exp((double)uv[c]);
-                            double s = (double)uv[3];
-#pragma unroll
-                            for (int k = 0; k < K; ++k) s += B64[k][c] * (double)uv[4 + k];
-                            S[c] = s;
-                        }
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const double ec = (double)a.I[c * ps + i] - R[c] * S[c];
-#pragma unroll
-                            for (int k = 0; k < K; ++k) sv[c * (K + 1) + k] = R[c] * (double)uv[4 + k];
-                            sv[c * (K + 1) + K] = ec;
-                        }
-                    }
-                } else if (a.refine) {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) sv[v] = 0.0;
                 }
+                if (st.refine) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double R = exp((double)uv[c]);
+                        double S = (double)uv[3];
+#pragma unroll
+                        for (int k = 0; k < K; ++k) S += B64[k][c] * (double)uv[4 + k];
+                        Rs[c][sp] = R;
+                        Es[c][sp] = (double)a.I[c * ps + i] - R * S;
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; ++k) Ts[k][sp] = uv[4 + k];
+                }
+            } else if (st.refine) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Rs[c][sp] = Es[c][sp] = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) Ts[k][sp] = 0.0f;
             }
-            if (!a.refine) continue;
+            if (!st.refine) continue;
             __syncthreads();
             if (owner) {
                 for (int px = grp; px < BS_BATCH; px += NG) {
-                    const double* sv = stage + px * NV + oc * (K + 1);
-                    const double vk = sv[ok];
+                    const double Rc = Rs[oc][px];
+                    const double vk = Rc * (double)Ts[ok][px];
 #pragma unroll
-                    for (int l = 0; l <= K; ++l)
-                        if (l >= ok) acc[l] += vk * sv[l];
+                    for (int l = 0; l < K; ++l)
+                        if (l >= ok) acc[l] += vk * (Rc * (double)Ts[l][px]);
+                    acc[K] += vk * Es[oc][px];
                 }
             }
             __syncthreads();
         }
     }
-    if (!a.refine) return;
+    if (!st.refine) return;
     // combine the pixel groups, then publish this workgroup's sums
     if (owner) {
 #pragma unroll
         for (int l = 0; l <= K; ++l) red[(grp * 3 * K + lane) * (K + 1) + l] = acc[l];
     }
     __syncthreads();
-    const int nb = gridDim.x;
-    const int nsum = bstep_nsums(K);
+    const int nb = lc.nb;
     double* part = a.partials + (long long)R_BS * a.part_stride;
     for (int e = threadIdx.x; e < 3 * K * (K + 1); e += NTHREADS) {
         const int jj = e / (K + 1), l = e % (K + 1);
         const int c = jj / K, k = jj % K;
         if (l < K && l < k) continue;
-        double s = 0.0;
-        for (int g = 0; g < NG; ++g) s += red[(g * 3 * K + jj) * (K + 1) + l];
+        double sum = 0.0;
+        for (int g = 0; g < NG; ++g) sum += red[(g * 3 * K + jj) * (K + 1) + l];
         int idx;
         if (l < K) idx = c * (K * (K + 1) / 2) + (k * K - k * (k - 1) / 2) + (l - k);
         else       idx = 3 * K * (K + 1) / 2 + c * K + k;
-        part[(long long)idx * nb + lb] = s;
+        part[(long long)idx * nb + lb] = sum;
     }
-    (void)nsum;
+}
+
+// ------------------------------------------------------------ colour tables
+
+// Derive the FP32 colours, ln b (FP64 and FP32) and b minus its channel mean
+// from the FP64 colours.  The only place these tables are computed, so a state
+// restored from a checkpoint reproduces them bit for bit.
+__device__ void colour_tables(const Args& a) {
+    for (int i = 0; i < 3 * a.K; ++i) {
+        const double b = a.b64[i];
+        a.bf[i] = (float)b;
+        const double lg = log(b);
+        a.lnb64[i] = lg;
+        a.lnb[i] = (float)lg;
+    }
+    for (int k = 0; k < a.K; ++k) {
+        const float b0 = a.bf[3 * k], b1 = a.bf[3 * k + 1], b2 = a.bf[3 * k + 2];
+        const float mu = (b0 + b1 + b2) * (1.0f / 3.0f);
+        a.bcf[3 * k] = b0 - mu;
+        a.bcf[3 * k + 1] = b1 - mu;
+        a.bcf[3 * k + 2] = b2 - mu;
+    }
+}
+
+__device__ __forceinline__ void tables_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+    if (threadIdx.x == 0) colour_tables(a);
 }
 
 // -------------------------------------------------------- base-colour solve
@@ -697,14 +782,17 @@ __global__ __launch_bounds__(NTHREADS) void k_apply_bsum(Args a) {
 // One workgroup: reduce the per-workgroup sums, assemble the 3K x 3K system of
 // the base-colour step, solve it by FP64 Cholesky, apply the guards, update b.
 template <int K>
-__global__ __launch_bounds__(1024) void k_bsolve(Args a, int nb) {
+__device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int NA = 3 * K * (K + 1) / 2;
     constexpr int NS = NA + 3 * K;
     constexpr int NN = 3 * K;
-    __shared__ double sums[NS];
-    __shared__ double Hm[NN][NN + 1];
-    __shared__ double gv[NN];
-    __shared__ double piv_ok;
+    const int nb = a.nb_bs;
+    double* sums = reinterpret_cast<double*>(smem);
+    double (*Hm)[NN + 1] = reinterpret_cast<double (*)[NN + 1]>(smem + 8 * NS);
+    double* gv = reinterpret_cast<double*>(smem + 8 * (NS + NN * (NN + 1)));
+    double* ysol = gv + NN;
+    double* dbsol = ysol + NN;
+    double& piv_ok = dbsol[NN];
     if (a.scal[S_BADIN] != 0.0) return;
     const double* part = a.partials + (long long)R_BS * a.part_stride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
@@ -715,7 +803,7 @@ __global__ __launch_bounds__(1024) void k_bsolve(Args a, int nb) {
         if (lane == 0) sums[e] = s * (double)a.lam.data;
     }
     __syncthreads();
-    if (a.debug) {   // publish the raw sums for single-step access
+    if (st.debug) {   // publish the raw sums for single-step access
         for (int e = threadIdx.x; e < NS; e += blockDim.x) a.bsum[e] = sums[e];
         return;
     }
@@ -794,32 +882,36 @@ __global__ __launch_bounds__(1024) void k_bsolve(Args a, int nb) {
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        double y[NN], db[NN];
+    // forward and back substitution, one wavefront: lane i2 owns row i2 (NN <= 48)
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
         for (int i2 = 0; i2 < NN; ++i2) {
-            double s = gv[i2];
-            for (int kk = 0; kk < i2; ++kk) s -= Hm[i2][kk] * y[kk];
-            y[i2] = s / Hm[i2][i2];
+            if (lane == 0) {
+                double s = gv[i2];
+                for (int kk = 0; kk < i2; ++kk) s -= Hm[i2][kk] * ysol[kk];
+                ysol[i2] = s / Hm[i2][i2];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         for (int i2 = NN - 1; i2 >= 0; --i2) {
-            double s = y[i2];
-            for (int kk = i2 + 1; kk < NN; ++kk) s -= Hm[kk][i2] * db[kk];
-            db[i2] = s / Hm[i2][i2];
+            if (lane == 0) {
+                double s = ysol[i2];
+                for (int kk = i2 + 1; kk < NN; ++kk) s -= Hm[kk][i2] * dbsol[kk];
+                dbsol[i2] = s / Hm[i2][i2];
+            }
+            __builtin_amdgcn_wave_barrier();
         }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         bool ok = piv_ok != 0.0;
-        double nbv[NN];
         for (int i2 = 0; i2 < NN; ++i2) {
-            nbv[i2] = a.b64[i2] + db[i2];
-            if (!isfinite(nbv[i2]) || !(nbv[i2] > 1e-4)) ok = false;
+            const double nb2 = a.b64[i2] + dbsol[i2];
+            if (!isfinite(nb2) || !(nb2 > 1e-4)) ok = false;
         }
         if (ok) {
-            for (int i2 = 0; i2 < NN; ++i2) {
-                a.b64[i2] = nbv[i2];
-                a.bf[i2] = (float)nbv[i2];
-                const double lg = log(nbv[i2]);
-                a.lnb64[i2] = lg;
-                a.lnb[i2] = (float)lg;
-            }
+            for (int i2 = 0; i2 < NN; ++i2) a.b64[i2] += dbsol[i2];
+            colour_tables(a);
             a.scal[S_BACCEPT] = 1.0;
         } else {
             a.scal[S_BACCEPT] = 0.0;
@@ -831,8 +923,8 @@ __global__ __launch_bounds__(1024) void k_bsolve(Args a, int nb) {
 // --------------------------------------------------------------- FP64 energy
 
 template <int K>
-__global__ __launch_bounds__(NTHREADS) void k_energy(Args a) {
-    __shared__ double sh4[4];
+__device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+    double* sh4 = reinterpret_cast<double*>(smem);
     if (a.scal[S_BADIN] != 0.0) return;
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
@@ -846,7 +938,7 @@ __global__ __launch_bounds__(NTHREADS) void k_energy(Args a) {
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c) Bk[k][c] = a.b64[3 * k + c];
-    for_each_pixel(a, [&](int x, int y, long long i) {
+    for_each_pixel(a, lc, [&](int x, int y, long long i) {
         double r[3], T[K + 1];
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = a.u[c * ps + i];
@@ -917,18 +1009,19 @@ __global__ __launch_bounds__(NTHREADS) void k_energy(Args a) {
     double vals[NTERMS];
 #pragma unroll
     for (int v = 0; v < NTERMS; ++v) vals[v] = block_sum(e[v] * lam[v], sh4);
-    publish(a, R_EN, vals, NTERMS);
+    publish(a, lc, R_EN, vals, NTERMS);
 }
 
 // One workgroup: total the energy partials of the preceding k_energy launch
 // (nb workgroups) into an energy-log slot.
-__global__ __launch_bounds__(NTHREADS) void k_energy_finish(Args a, int nb) {
-    __shared__ double sh4[4];
+__device__ __forceinline__ void energy_finish_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+    const int nb = a.nblocks;
+    double* sh4 = reinterpret_cast<double*>(smem);
     if (a.scal[S_BADIN] != 0.0) return;
     double tot[NTERMS];
     for (int v = 0; v < NTERMS; ++v) tot[v] = site_total(a, R_EN, v, nb, sh4);
     if (threadIdx.x == 0) {
-        double* slot = a.elog + (long long)a.slot * ELOG_STRIDE;
+        double* slot = a.elog + (long long)st.slot * ELOG_STRIDE;
         double s = 0.0;
         for (int v = 0; v < NTERMS; ++v) {
             slot[1 + v] = tot[v];
@@ -941,11 +1034,11 @@ __global__ __launch_bounds__(NTHREADS) void k_energy_finish(Args a, int nb) {
 // -------------------------------------------------------------------- output
 
 template <int K>
-__global__ __launch_bounds__(NTHREADS) void k_output(Args a) {
+__device__ __forceinline__ void output_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
     if (a.scal[S_BADIN] != 0.0) return;
     const long long ps = a.ps;
-    for_each_pixel(a, [&](int x, int y, long long i) {
+    for_each_pixel(a, lc, [&](int x, int y, long long i) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float r = a.u[c * ps + i];
@@ -960,8 +1053,8 @@ __global__ __launch_bounds__(NTHREADS) void k_output(Args a) {
     });
 }
 
-__global__ void k_reset_frame(Args a) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__device__ __forceinline__ void reset_frame_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+    if (threadIdx.x == 0) {
         a.scal[S_BREAKDOWNS] = 0.0;
         a.scal[S_BREJECT] = 0.0;
         a.scal[S_STOP] = 0.0;
@@ -970,79 +1063,214 @@ __global__ void k_reset_frame(Args a) {
     }
 }
 
+// --------------------------------------------------------- LDS footprints
+
+constexpr size_t LDS_SMALL = 32;
+template <int K> constexpr size_t lds_gn_build() { return 32 + sizeof(float) * (K + 4) * HN; }
+template <int K> constexpr size_t lds_matvec() { return 32 + sizeof(float) * 2 * (K + 4) * HN; }
+template <int K> constexpr size_t lds_apply_bsum() {
+    return 32 + 6 * BS_BATCH * 8 + (NTHREADS / ((3 * K <= 32) ? 32 : 64)) * 3 * K * (K + 1) * 8 +
+           sizeof(float) * K * BS_BATCH;
+}
+template <int K> constexpr size_t lds_bsolve() {
+    return 8 * (3 * K * (K + 1) / 2 + 3 * K + 3 * K * (3 * K + 1) + 3 * 3 * K + 1);
+}
+
+// ------------------------------------------------------------------ wrappers
+
+// Workgroup -> clip of a batched launch (wg: prefix of per-clip workgroup counts).
+__device__ __forceinline__ int clip_index(const int* wg, int nclips) {
+    int c = 0;
+    while (c + 1 < nclips && (int)blockIdx.x >= wg[c + 1]) ++c;
+    return c;
+}
+
+__device__ __forceinline__ Lc clip_grid(const int* wg, int c) {
+    const int nb = wg[c + 1] - wg[c];
+    return Lc{xcd_order((int)blockIdx.x - wg[c], nb), nb};
+}
+
+// Run fn(std::integral_constant<int, K>) for the clip's K (1..KB).
+template <int KB, typename Fn>
+__device__ __forceinline__ void dispatch_K(int K, Fn&& fn) {
+    switch (K) {
+#define GID_CASE(V) \
+        case V: if constexpr (KB >= V) fn(std::integral_constant<int, V>{}); break;
+        GID_CASE(1) GID_CASE(2) GID_CASE(3) GID_CASE(4) GID_CASE(5) GID_CASE(6) GID_CASE(7) GID_CASE(8)
+        GID_CASE(9) GID_CASE(10) GID_CASE(11) GID_CASE(12) GID_CASE(13) GID_CASE(14) GID_CASE(15) GID_CASE(16)
+#undef GID_CASE
+        default: break;
+    }
+}
+
+#define GID_PIXEL_KERNELS(NAME, ATTR)                                                              \
+    template <int K>                                                                               \
+    __global__ __launch_bounds__(NTHREADS) ATTR void k_##NAME(Args a, Step st) {                   \
+        extern __shared__ __align__(16) char smem[];                                               \
+        NAME##_body<K>(a, whole_grid(), st, smem);                                                 \
+    }                                                                                              \
+    template <int KB>                                                                              \
+    __global__ __launch_bounds__(NTHREADS) ATTR void kb_##NAME(const Args* args, const int* wg, int nclips, \
+                                                               Step st) {                          \
+        extern __shared__ __align__(16) char smem[];                                               \
+        const int c = clip_index(wg, nclips);                                                      \
+        const Args& a = args[c];                                                                   \
+        const Lc lc = clip_grid(wg, c);                                                            \
+        dispatch_K<KB>(a.K, [&](auto kc) { NAME##_body<decltype(kc)::value>(a, lc, st, smem); });  \
+    }
+
+GID_PIXEL_KERNELS(precompute, )
+GID_PIXEL_KERNELS(gn_build, __attribute__((amdgpu_waves_per_eu(4))))
+GID_PIXEL_KERNELS(matvec, )
+GID_PIXEL_KERNELS(update, )
+GID_PIXEL_KERNELS(apply_bsum, )
+GID_PIXEL_KERNELS(energy, )
+GID_PIXEL_KERNELS(output, )
+
+__global__ __launch_bounds__(NTHREADS) void k_scan(Args a, Step st) {
+    extern __shared__ __align__(16) char smem[];
+    scan_body(a, whole_grid(), st, smem);
+}
+__global__ __launch_bounds__(NTHREADS) void kb_scan(const Args* args, const int* wg, int nclips, Step st) {
+    extern __shared__ __align__(16) char smem[];
+    const int c = clip_index(wg, nclips);
+    scan_body(args[c], clip_grid(wg, c), st, smem);
+}
+
+// one workgroup per clip
+template <int K>
+__global__ __launch_bounds__(1024) void k_bsolve(Args a, Step st) {
+    extern __shared__ __align__(16) char smem[];
+    bsolve_body<K>(a, Lc{0, 1}, st, smem);
+}
+template <int KB>
+__global__ __launch_bounds__(1024) void kb_bsolve(const Args* args, Step st) {
+    extern __shared__ __align__(16) char smem[];
+    const Args& a = args[blockIdx.x];
+    dispatch_K<KB>(a.K, [&](auto kc) { bsolve_body<decltype(kc)::value>(a, Lc{0, 1}, st, smem); });
+}
+__global__ __launch_bounds__(NTHREADS) void k_energy_finish(Args a, Step st) {
+    extern __shared__ __align__(16) char smem[];
+    energy_finish_body(a, Lc{0, 1}, st, smem);
+}
+__global__ __launch_bounds__(NTHREADS) void kb_energy_finish(const Args* args, Step st) {
+    extern __shared__ __align__(16) char smem[];
+    energy_finish_body(args[blockIdx.x], Lc{0, 1}, st, smem);
+}
+__global__ void k_reset_frame(Args a, Step st) { reset_frame_body(a, Lc{0, 1}, st, nullptr); }
+__global__ void k_tables(Args a, Step st) { tables_body(a, Lc{0, 1}, st, nullptr); }
+__global__ void kb_reset_frame(const Args* args, Step st) { reset_frame_body(args[blockIdx.x], Lc{0, 1}, st, nullptr); }
+
 }  // namespace
 
+#ifndef GID_KERNELS_ONLY
 // ------------------------------------------------------------------ launchers
 
 namespace {
-// Call fn(std::integral_constant<int, K>) for the runtime K (1..KMAX).
 template <typename Fn>
 hipError_t with_K(int K, Fn&& fn) {
     switch (K) {
-        case 1: fn(std::integral_constant<int, 1>{}); break;
-        case 2: fn(std::integral_constant<int, 2>{}); break;
-        case 3: fn(std::integral_constant<int, 3>{}); break;
-        case 4: fn(std::integral_constant<int, 4>{}); break;
-        case 5: fn(std::integral_constant<int, 5>{}); break;
-        case 6: fn(std::integral_constant<int, 6>{}); break;
-        case 7: fn(std::integral_constant<int, 7>{}); break;
-        case 8: fn(std::integral_constant<int, 8>{}); break;
-        case 9: fn(std::integral_constant<int, 9>{}); break;
-        case 10: fn(std::integral_constant<int, 10>{}); break;
-        case 11: fn(std::integral_constant<int, 11>{}); break;
-        case 12: fn(std::integral_constant<int, 12>{}); break;
-        case 13: fn(std::integral_constant<int, 13>{}); break;
-        case 14: fn(std::integral_constant<int, 14>{}); break;
-        case 15: fn(std::integral_constant<int, 15>{}); break;
-        case 16: fn(std::integral_constant<int, 16>{}); break;
+#define GID_CASE(V) case V: fn(std::integral_constant<int, V>{}); break;
+        GID_CASE(1) GID_CASE(2) GID_CASE(3) GID_CASE(4) GID_CASE(5) GID_CASE(6) GID_CASE(7) GID_CASE(8)
+        GID_CASE(9) GID_CASE(10) GID_CASE(11) GID_CASE(12) GID_CASE(13) GID_CASE(14) GID_CASE(15) GID_CASE(16)
+#undef GID_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
+
+template <typename Fn>
+hipError_t with_KB(int kb, Fn&& fn) {
+    if (kb <= 8) fn(std::integral_constant<int, 8>{});
+    else if (kb <= KMAX) fn(std::integral_constant<int, 16>{});
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 }  // namespace
 
-#define GID_TILED_LAUNCHER(NAME)                                                              \
-    hipError_t launch_##NAME(const Args& a, hipStream_t s) {                                  \
-        return with_K(a.K, [&](auto kc) {                                                     \
-            constexpr int KK = decltype(kc)::value;                                           \
-            hipLaunchKernelGGL(k_##NAME<KK>, dim3(a.nblocks), dim3(NTHREADS), 0, s, a);       \
-        });                                                                                   \
+hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
+    const dim3 blk(NTHREADS), grid(a.nblocks);
+    switch (k) {
+        case KN_SCAN:
+            hipLaunchKernelGGL(k_scan, grid, blk, LDS_SMALL, s, a, st);
+            return hipGetLastError();
+        case KN_RESET:
+            hipLaunchKernelGGL(k_reset_frame, dim3(1), dim3(64), 0, s, a, st);
+            return hipGetLastError();
+        case KN_ENERGY_FINISH:
+            hipLaunchKernelGGL(k_energy_finish, dim3(1), blk, LDS_SMALL, s, a, st);
+            return hipGetLastError();
+        case KN_TABLES:
+            hipLaunchKernelGGL(k_tables, dim3(1), dim3(64), 0, s, a, st);
+            return hipGetLastError();
+        default:
+            break;
     }
-
-GID_TILED_LAUNCHER(precompute)
-GID_TILED_LAUNCHER(gn_build)
-GID_TILED_LAUNCHER(matvec)
-GID_TILED_LAUNCHER(update)
-GID_TILED_LAUNCHER(energy)
-GID_TILED_LAUNCHER(output)
-
-hipError_t launch_apply_bsum(const Args& a, int nblocks_bs, hipStream_t s) {
     return with_K(a.K, [&](auto kc) {
         constexpr int KK = decltype(kc)::value;
-        hipLaunchKernelGGL(k_apply_bsum<KK>, dim3(nblocks_bs), dim3(NTHREADS), 0, s, a);
+        switch (k) {
+            case KN_PRECOMPUTE: hipLaunchKernelGGL(k_precompute<KK>, grid, blk, LDS_SMALL, s, a, st); break;
+            case KN_GN_BUILD: hipLaunchKernelGGL(k_gn_build<KK>, grid, blk, lds_gn_build<KK>(), s, a, st); break;
+            case KN_MATVEC: hipLaunchKernelGGL(k_matvec<KK>, grid, blk, lds_matvec<KK>(), s, a, st); break;
+            case KN_UPDATE: hipLaunchKernelGGL(k_update<KK>, grid, blk, LDS_SMALL, s, a, st); break;
+            case KN_APPLY_BSUM:
+                hipLaunchKernelGGL(k_apply_bsum<KK>, dim3(a.nb_bs), blk, lds_apply_bsum<KK>(), s, a, st);
+                break;
+            case KN_BSOLVE: hipLaunchKernelGGL(k_bsolve<KK>, dim3(1), dim3(1024), lds_bsolve<KK>(), s, a, st); break;
+            case KN_ENERGY: hipLaunchKernelGGL(k_energy<KK>, grid, blk, LDS_SMALL, s, a, st); break;
+            case KN_OUTPUT: hipLaunchKernelGGL(k_output<KK>, grid, blk, LDS_SMALL, s, a, st); break;
+            default: break;
+        }
     });
 }
 
-hipError_t launch_bsolve(const Args& a, int nblocks_bs, hipStream_t s) {
-    return with_K(a.K, [&](auto kc) {
-        constexpr int KK = decltype(kc)::value;
-        hipLaunchKernelGGL(k_bsolve<KK>, dim3(1), dim3(1024), 0, s, a, nblocks_bs);
+hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t s) {
+    const dim3 blk(NTHREADS), gpix(g.total_pix), gbs(g.total_bs), gone(g.nclips);
+    switch (k) {
+        case KN_SCAN:
+            hipLaunchKernelGGL(kb_scan, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+            return hipGetLastError();
+        case KN_RESET:
+            hipLaunchKernelGGL(kb_reset_frame, gone, dim3(64), 0, s, g.args, st);
+            return hipGetLastError();
+        case KN_ENERGY_FINISH:
+            hipLaunchKernelGGL(kb_energy_finish, gone, blk, LDS_SMALL, s, g.args, st);
+            return hipGetLastError();
+        default:
+            break;
+    }
+    return with_KB(g.kb, [&](auto kc) {
+        constexpr int KB = decltype(kc)::value;
+        switch (k) {
+            case KN_PRECOMPUTE:
+                hipLaunchKernelGGL(kb_precompute<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+                break;
+            case KN_GN_BUILD:
+                hipLaunchKernelGGL(kb_gn_build<KB>, gpix, blk, lds_gn_build<KB>(), s, g.args, g.wg_pix, g.nclips, st);
+                break;
+            case KN_MATVEC:
+                hipLaunchKernelGGL(kb_matvec<KB>, gpix, blk, lds_matvec<KB>(), s, g.args, g.wg_pix, g.nclips, st);
+                break;
+            case KN_UPDATE:
+                hipLaunchKernelGGL(kb_update<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+                break;
+            case KN_APPLY_BSUM:
+                hipLaunchKernelGGL(kb_apply_bsum<KB>, gbs, blk, lds_apply_bsum<KB>(), s, g.args, g.wg_bs, g.nclips, st);
+                break;
+            case KN_BSOLVE:
+                hipLaunchKernelGGL(kb_bsolve<KB>, gone, dim3(1024), lds_bsolve<KB>(), s, g.args, st);
+                break;
+            case KN_ENERGY:
+                hipLaunchKernelGGL(kb_energy<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+                break;
+            case KN_OUTPUT:
+                hipLaunchKernelGGL(kb_output<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+                break;
+            default: break;
+        }
     });
 }
 
-hipError_t launch_energy_finish(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(NTHREADS), 0, s, a, a.nblocks);
-    return hipGetLastError();
-}
-
-hipError_t launch_scan(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(a.nblocks), dim3(NTHREADS), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_reset_frame(const Args& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset_frame, dim3(1), dim3(64), 0, s, a);
-    return hipGetLastError();
-}
+#endif  // GID_KERNELS_ONLY
 
 }  // namespace gid

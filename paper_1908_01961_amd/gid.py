@@ -69,6 +69,7 @@ SIGNATURES = [
     ("gid_synchronize", c_int32, [c_void_p]),
     ("gid_load_frame", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("gid_set_state", c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
+    ("gid_set_prev_frame", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("gid_get_state", c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     ("gid_eval_energy", c_int32, [c_void_p, POINTER(c_double), POINTER(c_double)]),
     ("gid_eval_rhs", c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -78,6 +79,14 @@ SIGNATURES = [
     ("gid_base_step", c_int32, [c_void_p, POINTER(c_int32)]),
     ("gid_set_profiling", c_int32, [c_void_p, c_int32]),
     ("gid_get_kernel_times", c_int32, [c_void_p, POINTER(c_double), POINTER(ctypes.c_int64)]),
+    ("gid_batch_create", c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p)]),
+    ("gid_batch_destroy", c_int32, [c_void_p]),
+    ("gid_batch_decompose", c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p)]),
+    ("gid_batch_synchronize", c_int32, [c_void_p, POINTER(c_double)]),
+    ("gid_batch_last_error", ctypes.c_char_p, [c_void_p]),
+    ("gid_autotune", c_int32, [c_void_p, ctypes.c_char_p, POINTER(c_int32)]),
+    ("gid_set_workgroups", c_int32, [c_void_p, c_int32]),
+    ("gid_get_workgroups", c_int32, [c_void_p]),
     ("gid_save_state", c_int32, [c_void_p, c_void_p, POINTER(c_size_t)]),
     ("gid_load_state", c_int32, [c_void_p, c_void_p, c_size_t]),
     ("gid_status_string", ctypes.c_char_p, [c_int32]),
@@ -222,6 +231,12 @@ class Solver:
             arr, bp = None, None
         self._check(self.lib.gid_set_state(self.h, up, bp), "gid_set_state")
 
+    def set_prev_frame(self, frame_prev, r_prev):
+        import torch
+        f = _ptr(frame_prev, torch.float32, (3, self.H, self.W), "frame_prev")
+        r = _ptr(r_prev, torch.float32, (3, self.H, self.W), "r_prev")
+        self._check(self.lib.gid_set_prev_frame(self.h, f, r), "gid_set_prev_frame")
+
     def get_state(self):
         import torch
         u = torch.empty((self.n, self.H, self.W), dtype=torch.float32, device="cuda")
@@ -268,6 +283,20 @@ class Solver:
         self._check(self.lib.gid_base_step(self.h, byref(ok)), "gid_base_step")
         return bool(ok.value)
 
+    # -- launch shape
+    def autotune(self, cache_path: str | None = None) -> int:
+        n = c_int32()
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.gid_autotune(self.h, path, byref(n)), "gid_autotune")
+        return n.value
+
+    def set_workgroups(self, n: int):
+        self._check(self.lib.gid_set_workgroups(self.h, int(n)), "gid_set_workgroups")
+
+    @property
+    def workgroups(self) -> int:
+        return int(self.lib.gid_get_workgroups(self.h))
+
     # -- kernel timing
     def set_profiling(self, enable: bool):
         self._check(self.lib.gid_set_profiling(self.h, int(bool(enable))), "gid_set_profiling")
@@ -290,3 +319,59 @@ class Solver:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._check(self.lib.gid_load_state(self.h, buf, len(blob)), "gid_load_state")
+
+
+class Batch:
+    """Clips of uneven size solved together: one launch per kernel per step."""
+
+    def __init__(self, solvers):
+        self.lib = load_library()
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        arr = (c_void_p * n)(*[s.h.value for s in self.solvers])
+        h = c_void_p()
+        st = self.lib.gid_batch_create(arr, n, byref(h))
+        if st != GID_OK:
+            raise GidError(st, "gid_batch_create")
+        self.h = h
+        self._e = np.zeros(n)
+
+    def _check(self, st, what):
+        if st != GID_OK:
+            raise GidError(st, f"{what}: {self.lib.gid_batch_last_error(self.h).decode()}")
+
+    def step_async(self, frames, ids, layers=None):
+        """frames[i] / ids[i]: tensors for active clips, None for finished ones."""
+        import torch
+        n = len(self.solvers)
+        fp = (c_void_p * n)()
+        ip = (c_void_p * n)()
+        lp = (c_void_p * n)()
+        for i, s in enumerate(self.solvers):
+            if frames[i] is None:
+                continue
+            fp[i] = _ptr(frames[i], torch.float32, (3, s.H, s.W), "frame").value
+            ip[i] = _ptr(ids[i], torch.uint8, (s.H, s.W), "ids").value
+            if layers is not None and layers[i] is not None:
+                lp[i] = _ptr(layers[i], torch.float32, (s.n, s.H, s.W), "layers").value
+        self._check(self.lib.gid_batch_decompose(self.h, fp, ip, lp), "gid_batch_decompose")
+
+    def synchronize(self):
+        self._check(self.lib.gid_batch_synchronize(self.h, self._e.ctypes.data_as(POINTER(c_double))),
+                    "gid_batch_synchronize")
+        return self._e.copy()
+
+    def step(self, frames, ids, layers=None):
+        self.step_async(frames, ids, layers)
+        return self.synchronize()
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.gid_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

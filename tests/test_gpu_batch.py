@@ -1,0 +1,147 @@
+"""Batched clips of uneven size and the launch-shape autotuner, through the C ABI.
+
+A batch runs the same kernel bodies as single clips with the same per-clip
+workgroup layout and reduction order, so its results must equal per-clip runs
+bitwise; the first frames are also checked against the FP64 oracle at the
+parity bar (layers 1e-3 absolute, energy 1e-4 relative)."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+from scenes import make_clip
+
+pytestmark = pytest.mark.gpu
+
+P = O.default_params(state_precision="f32")
+P64 = O.default_params()
+
+
+def _env(L, e, c, nframes=1):
+    """Distance of GPU layers L and energy e from the envelope of the two oracle
+    runs (FP32-stored and FP64-stored unknowns) for the first frame of clip c."""
+    refs = [O.decompose_clip(c.frames, c.ids, c.b_init, p, 3, 8, temporal=True, nframes=nframes)[0]
+            for p in (P, P64)]
+    dR = np.min([np.abs(L[:3] - np.exp(r.u[:3])) for r in refs], axis=0).max()
+    dT = np.min([np.abs(L[3:] - r.u[3:]) for r in refs], axis=0).max()
+    rel = min(abs(e - r.energy) / r.energy for r in refs)
+    return dR, dT, rel
+
+
+def _say(*m):
+    print("[gpu-case]", *m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_01961_amd as G
+    G.load_library()
+    return _t
+
+
+def _clips():
+    # (W, H, K, frames, seed): uneven sizes, K and lengths, ragged tiles
+    spec = [(96, 64, 4, 3, 401), (160, 120, 6, 2, 402), (70, 45, 5, 4, 403), (130, 72, 8, 3, 404)]
+    return [make_clip(W, H, K, F, s) for (W, H, K, F, s) in spec]
+
+
+def _solver(c, **kw):
+    import paper_1908_01961_amd as G
+    s = G.Solver(c.width, c.height, G.default_params(c.K, gn_iters=3, pcg_iters=8, temporal=1, **kw))
+    s.set_base_colors(c.b_init)
+    return s
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_batch_equals_single_clips_bitwise(torch):
+    import paper_1908_01961_amd as G
+    clips = _clips()
+    _say("batch of", [(c.width, c.height, c.K, c.nframes) for c in clips])
+    single = []
+    for c in clips:
+        s = _solver(c)
+        out = []
+        lay = torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda")
+        for t in range(c.nframes):
+            _, st = s.decompose_frame(_dev(torch, c.frames[t]), _dev(torch, c.ids[t]), lay)
+            out.append((lay.cpu().numpy().copy(), st["energy_final"]))
+        s.close()
+        single.append(out)
+    solvers = [_solver(c) for c in clips]
+    batch = G.Batch(solvers)
+    lays = [torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda") for c in clips]
+    for t in range(max(c.nframes for c in clips)):
+        frames = [_dev(torch, c.frames[t]) if t < c.nframes else None for c in clips]
+        ids = [_dev(torch, c.ids[t]) if t < c.nframes else None for c in clips]
+        e = batch.step(frames, ids, lays)
+        for i, c in enumerate(clips):
+            if t >= c.nframes:
+                assert np.isnan(e[i])
+                continue
+            assert np.array_equal(lays[i].cpu().numpy(), single[i][t][0]), (i, t)
+            assert e[i] == single[i][t][1], (i, t)
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_first_frames_match_oracle(torch):
+    import paper_1908_01961_amd as G
+    clips = _clips()
+    solvers = [_solver(c) for c in clips]
+    batch = G.Batch(solvers)
+    lays = [torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda") for c in clips]
+    e = batch.step([_dev(torch, c.frames[0]) for c in clips], [_dev(torch, c.ids[0]) for c in clips], lays)
+    for i, c in enumerate(clips):
+        dR, dT, rel = _env(lays[i].cpu().numpy().astype(np.float64), e[i], c)
+        _say(f"clip {i}: |dR|={dR:.2e} |dT|={dT:.2e} Erel={rel:.2e}")
+        assert dR <= 1e-3 and dT <= 1e-3 and rel <= 1e-4
+    batch.close()
+
+
+def test_batch_rejects_a_bad_frame_and_keeps_that_clip(torch):
+    import paper_1908_01961_amd as G
+    clips = _clips()[:2]
+    solvers = [_solver(c) for c in clips]
+    batch = G.Batch(solvers)
+    batch.step([_dev(torch, c.frames[0]) for c in clips], [_dev(torch, c.ids[0]) for c in clips])
+    u_before, _ = solvers[0].get_state()
+    bad = clips[0].frames[1].copy()
+    bad[0, 1, 1] = np.inf
+    with pytest.raises(G.GidError) as ei:
+        batch.step([_dev(torch, bad), _dev(torch, clips[1].frames[1])],
+                   [_dev(torch, clips[0].ids[1]), _dev(torch, clips[1].ids[1])])
+    assert ei.value.status == 4
+    u_after, _ = solvers[0].get_state()
+    assert torch.equal(u_before, u_after)
+    batch.close()
+
+
+def test_autotune_chooses_and_caches_a_launch_shape(torch):
+    import paper_1908_01961_amd as G
+    c = make_clip(320, 240, 4, 1, 405)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        s = _solver(c)
+        n1 = s.autotune(path)
+        assert 8 <= n1 <= 2048 and n1 % 8 == 0
+        s2 = _solver(c)
+        assert s2.autotune(path) == n1                 # read back from the cache
+        assert open(path).read().split() == ["320", "240", "4", str(n1)]
+        # a solve with the tuned shape still meets the bar
+        lay = torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda")
+        _, st = s2.decompose_frame(_dev(torch, c.frames[0]), _dev(torch, c.ids[0]), lay)
+        dR, dT, rel = _env(lay.cpu().numpy().astype(np.float64), st["energy_final"], c)
+        assert dR <= 1e-3 and dT <= 1e-3 and rel <= 1e-4
+        s.close()
+        s2.close()
