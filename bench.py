@@ -60,6 +60,9 @@ def main() -> int:
     ap.add_argument("--frames", type=int, default=None, help="frames per clip (default: the workload's)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of graph replay")
     ap.add_argument("--cpu-frames", type=int, default=3, help="oracle sample size in frames (0: skip)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB device-to-device 5 times: a plain copy "
+                         "of known size for scaling hardware byte counters (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver is single-GPU (clips would shard across GPUs with "
@@ -166,6 +169,14 @@ def main() -> int:
     }
     print(json.dumps(out), flush=True)
     solver.close()
+    if args.calib_copy_mib > 0:
+        nbytes = args.calib_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: 5 x {nbytes} bytes read and written", file=sys.stderr, flush=True)
     return 0
 
 

@@ -52,11 +52,12 @@ class FrameResult:
     energies: list = field(default_factory=list)   # (label, E) after each half-step
     pcg: list = field(default_factory=list)        # per layer step: {"rz", "iters"}
     fd: Optional[FrameData] = None
+    starts: list = field(default_factory=list)     # unknowns at the start of every GN step (keep_starts)
 
 
 def decompose_frame(I, ids, b, b_init, p: OracleParams, G: int, P: int, *, u0=None,
                     prev=None, refine: bool = True, solver: str = "pcg",
-                    record: bool = True) -> FrameResult:
+                    record: bool = True, keep_starts: bool = False) -> FrameResult:
     """Run the fixed schedule on one frame.
 
     prev: (C_prev, r_prev) of the previous frame for the temporal prior, or None.
@@ -65,8 +66,10 @@ def decompose_frame(I, ids, b, b_init, p: OracleParams, G: int, P: int, *, u0=No
     fd = prepare_frame(I, ids, p, *(prev if prev is not None else (None, None)))
     b = np.asarray(b, np.float64).copy()
     u = store(init_state(fd.I, fd.ids, b), p) if u0 is None else np.asarray(u0, np.float64).copy()
-    energies, infos = [], []
+    energies, infos, starts = [], [], []
     for _ in range(G):
+        if keep_starts:
+            starts.append(u.copy())
         lin = linearise(u, b, fd, p)
         if solver == "pcg":
             delta, info = pcg(lin, P)
@@ -83,12 +86,12 @@ def decompose_frame(I, ids, b, b_init, p: OracleParams, G: int, P: int, *, u0=No
             if record:
                 energies.append(("B", total_energy(u, b, fd, p)))
     E = energies[-1][1] if (record and energies) else total_energy(u, b, fd, p)
-    return FrameResult(u=u, b=b, energy=E, energies=energies, pcg=infos, fd=fd)
+    return FrameResult(u=u, b=b, energy=E, energies=energies, pcg=infos, fd=fd, starts=starts)
 
 
 def decompose_clip(frames, ids, b_init, p: OracleParams, G: int, P: int, *, temporal: bool = True,
                    refine_mode: str = "every", solver: str = "pcg", nframes: int | None = None,
-                   record: bool = True):
+                   record: bool = True, keep_starts: bool = False):
     """Decompose frames in order with warm starts; returns the list of FrameResult.
 
     refine_mode: "every" (B-step in every outer iteration of every frame),
@@ -103,7 +106,7 @@ def decompose_clip(frames, ids, b_init, p: OracleParams, G: int, P: int, *, temp
         refine = refine_mode == "every" or (refine_mode == "first" and t == 0)
         res = decompose_frame(frames[t], ids[t], b, b_init, p, G, P, u0=u,
                               prev=prev if temporal else None, refine=refine, solver=solver,
-                              record=record)
+                              record=record, keep_starts=keep_starts)
         out.append(res)
         u, b = res.u, res.b
         prev = (res.fd.C, u[:3].copy())

@@ -11,7 +11,8 @@
 // halo rows a tile shares with its vertical neighbours stay in that XCD's L2.
 //
 // Grids are persistent-style: at most a few workgroups per CU, each owning a
-// contiguous chunk of tiles, so a launch produces at most ~1024 partial sums.
+// contiguous chunk of tiles (one tile each while the frame has at most 2048
+// tiles), so a launch produces at most 2048 partial sums.
 // Every kernel is a body over (clip descriptor, launch context, step); a
 // single-clip launch runs it over its whole grid, a batched launch runs the
 // bodies of several clips of uneven size and K in one grid, each workgroup
@@ -146,11 +147,13 @@ __device__ __forceinline__ float* p_new(const Args& a, int i) { return (i & 1) ?
 __device__ __forceinline__ float* p_old(const Args& a, int i) { return (i == 0 || !((i - 1) & 1)) ? a.pA : a.pB; }
 
 // p of the current PCG iteration at plane element j: the stored p0 for the first
-// iteration, z + beta p_old afterwards (recomputed identically by every reader).
-__device__ __forceinline__ float p_at(const Args& a, const float* pold, bool first, long long j, double beta) {
+// iteration, z + beta p_old afterwards in FP32 (a PCG vector operation; beta
+// itself is the FP64 ratio of two FP64 dot products, rounded once), recomputed
+// identically by every reader.
+__device__ __forceinline__ float p_at(const Args& a, const float* pold, bool first, long long j, float beta) {
     if (first) return pold[j];
     const float z = a.res[j] * a.minv[j];
-    return (float)((double)z + beta * (double)pold[j]);
+    return fmaf(beta, pold[j], z);
 }
 
 // --------------------------------------------------------------- input scan
@@ -457,6 +460,7 @@ __device__ __forceinline__ void matvec_body(const Args& a, const Lc& lc, const S
     }
     // single-step access applies J^T J to a caller vector
     const bool pfirst = st.debug || st.iter == 0;
+    const float betaf = (float)beta;
     const float* pold = st.debug ? a.pdebug : p_old(a, st.iter);
     float* pnw = p_new(a, st.iter);
     Basis<K> bs;
@@ -476,11 +480,12 @@ __device__ __forceinline__ void matvec_body(const Args& a, const Lc& lc, const S
             const int gx = x0 + idx % HW - 1, gy = y0 + idx / HW - 1;
             const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
             const long long gi = (long long)gy * W + gx;
-#pragma unroll 2
-            for (int v = 0; v < N; ++v) {
-                Ul[v * HN + idx] = in ? a.u[v * ps + gi] : 0.0f;
-                Pl[v * HN + idx] = in ? p_at(a, pold, pfirst, v * ps + gi, beta) : 0.0f;
-            }
+            // all u loads, then all p loads, each fully unrolled so every load of
+            // the element is in flight before the first LDS store
+#pragma unroll
+            for (int v = 0; v < N; ++v) Ul[v * HN + idx] = in ? a.u[v * ps + gi] : 0.0f;
+#pragma unroll
+            for (int v = 0; v < N; ++v) Pl[v * HN + idx] = in ? p_at(a, pold, pfirst, v * ps + gi, betaf) : 0.0f;
         }
         __syncthreads();
         const int x = x0 + lx, y = y0 + ly;
@@ -1105,12 +1110,12 @@ __device__ __forceinline__ void dispatch_K(int K, Fn&& fn) {
 
 #define GID_PIXEL_KERNELS(NAME, ATTR)                                                              \
     template <int K>                                                                               \
-    __global__ __launch_bounds__(NTHREADS) ATTR void k_##NAME(Args a, Step st) {                   \
+    __global__ __launch_bounds__(NTHREADS) ATTR(K) void k_##NAME(Args a, Step st) {                \
         extern __shared__ __align__(16) char smem[];                                               \
         NAME##_body<K>(a, whole_grid(), st, smem);                                                 \
     }                                                                                              \
     template <int KB>                                                                              \
-    __global__ __launch_bounds__(NTHREADS) ATTR void kb_##NAME(const Args* args, const int* wg, int nclips, \
+    __global__ __launch_bounds__(NTHREADS) ATTR(KB) void kb_##NAME(const Args* args, const int* wg, int nclips, \
                                                                Step st) {                          \
         extern __shared__ __align__(16) char smem[];                                               \
         const int c = clip_index(wg, nclips);                                                      \
@@ -1119,13 +1124,27 @@ __device__ __forceinline__ void dispatch_K(int K, Fn&& fn) {
         dispatch_K<KB>(a.K, [&](auto kc) { NAME##_body<decltype(kc)::value>(a, lc, st, smem); });  \
     }
 
-GID_PIXEL_KERNELS(precompute, )
-GID_PIXEL_KERNELS(gn_build, __attribute__((amdgpu_waves_per_eu(4))))
-GID_PIXEL_KERNELS(matvec, )
-GID_PIXEL_KERNELS(update, )
-GID_PIXEL_KERNELS(apply_bsum, )
-GID_PIXEL_KERNELS(energy, )
-GID_PIXEL_KERNELS(output, )
+// Occupancy targets.  The matvec's LDS tile limits a CU to lds_waves<K>()
+// workgroups (one wavefront of each per SIMD).  For K <= 6 the unconstrained
+// register allocation lands a few registers above that occupancy (K = 6: 100
+// VGPRs, four waves per SIMD instead of the five the LDS allows), so the
+// allocator is held to it; for larger K the natural allocation already fits.
+template <int K> constexpr int lds_waves() {
+    constexpr int w = (int)((160 * 1024) / lds_matvec<K>());
+    return w > 8 ? 8 : (w < 1 ? 1 : w);
+}
+template <int K> constexpr int mv_waves() { return K <= 6 ? lds_waves<K>() : 1; }
+#define GID_NO_ATTR(T)
+#define GID_GN_ATTR(T) __attribute__((amdgpu_waves_per_eu(4)))
+#define GID_MV_ATTR(T) __attribute__((amdgpu_waves_per_eu(mv_waves<T>())))
+
+GID_PIXEL_KERNELS(precompute, GID_NO_ATTR)
+GID_PIXEL_KERNELS(gn_build, GID_GN_ATTR)
+GID_PIXEL_KERNELS(matvec, GID_MV_ATTR)
+GID_PIXEL_KERNELS(update, GID_NO_ATTR)
+GID_PIXEL_KERNELS(apply_bsum, GID_NO_ATTR)
+GID_PIXEL_KERNELS(energy, GID_NO_ATTR)
+GID_PIXEL_KERNELS(output, GID_NO_ATTR)
 
 __global__ __launch_bounds__(NTHREADS) void k_scan(Args a, Step st) {
     extern __shared__ __align__(16) char smem[];

@@ -12,23 +12,19 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import compare_frame
 from scenes import make_clip
 
 pytestmark = pytest.mark.gpu
 
 P = O.default_params(state_precision="f32")
-P64 = O.default_params()
 
 
-def _env(L, e, c, nframes=1):
-    """Distance of GPU layers L and energy e from the envelope of the two oracle
-    runs (FP32-stored and FP64-stored unknowns) for the first frame of clip c."""
-    refs = [O.decompose_clip(c.frames, c.ids, c.b_init, p, 3, 8, temporal=True, nframes=nframes)[0]
-            for p in (P, P64)]
-    dR = np.min([np.abs(L[:3] - np.exp(r.u[:3])) for r in refs], axis=0).max()
-    dT = np.min([np.abs(L[3:] - r.u[3:]) for r in refs], axis=0).max()
-    rel = min(abs(e - r.energy) / r.energy for r in refs)
-    return dR, dT, rel
+def _check_first_frame(L, b, e, c, label):
+    """First frame of clip c against the oracle (3x8 schedule), as in the single-clip tests."""
+    ref = O.decompose_clip(c.frames, c.ids, c.b_init, P, 3, 8, temporal=True, nframes=1, keep_starts=True)[0]
+    alt = O.decompose_clip(c.frames, c.ids, c.b_init, O.default_params(), 3, 8, temporal=True, nframes=1)[0]
+    return compare_frame(L, b, e, ref, 8, label, _say, alt)
 
 
 def _say(*m):
@@ -103,9 +99,8 @@ def test_batch_first_frames_match_oracle(torch):
     lays = [torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda") for c in clips]
     e = batch.step([_dev(torch, c.frames[0]) for c in clips], [_dev(torch, c.ids[0]) for c in clips], lays)
     for i, c in enumerate(clips):
-        dR, dT, rel = _env(lays[i].cpu().numpy().astype(np.float64), e[i], c)
-        _say(f"clip {i}: |dR|={dR:.2e} |dT|={dT:.2e} Erel={rel:.2e}")
-        assert dR <= 1e-3 and dT <= 1e-3 and rel <= 1e-4
+        _, b = solvers[i].get_state()
+        _check_first_frame(lays[i].cpu().numpy().astype(np.float64), b, e[i], c, f"batch clip {i}:")
     batch.close()
 
 
@@ -140,8 +135,7 @@ def test_autotune_chooses_and_caches_a_launch_shape(torch):
         assert open(path).read().split() == ["320", "240", "4", str(n1)]
         # a solve with the tuned shape still meets the bar
         lay = torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda")
-        _, st = s2.decompose_frame(_dev(torch, c.frames[0]), _dev(torch, c.ids[0]), lay)
-        dR, dT, rel = _env(lay.cpu().numpy().astype(np.float64), st["energy_final"], c)
-        assert dR <= 1e-3 and dT <= 1e-3 and rel <= 1e-4
+        b, st = s2.decompose_frame(_dev(torch, c.frames[0]), _dev(torch, c.ids[0]), lay)
+        _check_first_frame(lay.cpu().numpy().astype(np.float64), b, st["energy_final"], c, "tuned launch:")
         s.close()
         s2.close()
