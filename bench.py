@@ -36,6 +36,25 @@ def algorithmic_bytes(n: int, tau: int, G: int, P: int) -> dict:
                 frame=4 * G * (P * (7 * n + 1 + tau) + 7 * n + 7 + 3 * tau))
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary of this workload, or None when there is none or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    src = os.path.join(ROOT, "paper_1908_01961_amd", "csrc", "gid_kernels.hip")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"kernel=(\S+) traffic_bytes_per_launch=(\d+) kernel_source_sha256_16=([0-9a-f]+)", text)
+    if not m or m.group(1) != kernel or m.group(3) != h:
+        return None
+    return int(m.group(2))
+
+
 def cpu_baseline(clip, G, P, frames):
     from threadpoolctl import threadpool_limits
     import oracle as O
@@ -131,7 +150,7 @@ def main() -> int:
     frame_ms = ms_per_step / F
     frame_gbs = ab["frame"] * W_ * H_ / (frame_ms / 1e3) / 1e9
     roofline = dict(bound="hbm", kernel="k_matvec", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic("k_matvec", args.workload),
                     algorithmic_bytes_per_launch=mv_bytes, avg_launch_us=round(mv_avg_s * 1e6, 2))
     kernels = {k: dict(avg_us=round(v["ms"] * 1e3 / v["launches"], 2), launches=v["launches"],
                        share=round(v["ms"] / max(1e-12, sum(x["ms"] for x in kt.values())), 4))
