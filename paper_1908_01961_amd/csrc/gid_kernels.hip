@@ -135,6 +135,14 @@ __device__ __forceinline__ float rcp_pos(float x) { return __builtin_amdgcn_rcpf
 
 __device__ __forceinline__ float w_pair(float a, float b, float eps) { return rcp_pos(fabsf(b - a) + eps); }
 
+// Value of a double held by lane `src` of the wavefront (src uniform).
+__device__ __forceinline__ double rdlane(double v, int src) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ void load3(const float* base, long long ps, long long i, float* v) {
     v[0] = base[i];
     v[1] = base[ps + i];
@@ -642,6 +650,7 @@ __device__ __forceinline__ void update_body(const Args& a, const Lc& lc, const S
 // ---------------------------------------------------- apply + base-colour sums
 
 constexpr int BS_BATCH = NTHREADS;   // pixels staged in LDS per round (one per thread)
+constexpr int BS_STRIDE = BS_BATCH + 1;   // padded row: rows of one pixel fall in different banks
 
 template <int K>
 __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
@@ -650,11 +659,11 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
     constexpr int NG = NTHREADS / GS;
     // per staged pixel: R_c and the data residual e_c in FP64, T_k (k >= 1) in FP32
     double* sh4 = reinterpret_cast<double*>(smem);
-    double (*Rs)[BS_BATCH] = reinterpret_cast<double (*)[BS_BATCH]>(smem + 32);
-    double (*Es)[BS_BATCH] = reinterpret_cast<double (*)[BS_BATCH]>(smem + 32 + 3 * BS_BATCH * 8);
-    double* red = reinterpret_cast<double*>(smem + 32 + 6 * BS_BATCH * 8);
-    float (*Ts)[BS_BATCH] = reinterpret_cast<float (*)[BS_BATCH]>(smem + 32 + 6 * BS_BATCH * 8 +
-                                                                    NG * 3 * K * (K + 1) * 8);
+    double (*Rs)[BS_STRIDE] = reinterpret_cast<double (*)[BS_STRIDE]>(smem + 32);
+    double (*Es)[BS_STRIDE] = reinterpret_cast<double (*)[BS_STRIDE]>(smem + 32 + 3 * BS_STRIDE * 8);
+    double* red = reinterpret_cast<double*>(smem + 32 + 6 * BS_STRIDE * 8);
+    float (*Ts)[BS_STRIDE] = reinterpret_cast<float (*)[BS_STRIDE]>(smem + 32 + 6 * BS_STRIDE * 8 +
+                                                                      NG * 3 * K * (K + 1) * 8);
     if (a.scal[S_BADIN] != 0.0) return;
     if (st.log_rz && a.scal[S_STOP] == 0.0) {
         // <r, z> after the last PCG iteration (site of iteration pcg_iters - 1)
@@ -722,13 +731,19 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
             if (!st.refine) continue;
             __syncthreads();
             if (owner) {
+                // the whole row k of the Gram block, branch-free so every LDS read of a
+                // pixel is in flight at once; entries l < k are discarded at the end
+#pragma unroll 2
                 for (int px = grp; px < BS_BATCH; px += NG) {
                     const double Rc = Rs[oc][px];
-                    const double vk = Rc * (double)Ts[ok][px];
+                    float tl[K];
 #pragma unroll
-                    for (int l = 0; l < K; ++l)
-                        if (l >= ok) acc[l] += vk * (Rc * (double)Ts[l][px]);
-                    acc[K] += vk * Es[oc][px];
+                    for (int l = 0; l < K; ++l) tl[l] = Ts[l][px];
+                    const double vk = Rc * (double)Ts[ok][px];
+                    const double ec = Es[oc][px];
+#pragma unroll
+                    for (int l = 0; l < K; ++l) acc[l] += vk * (Rc * (double)tl[l]);
+                    acc[K] += vk * ec;
                 }
             }
             __syncthreads();
@@ -759,30 +774,35 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
 // ------------------------------------------------------------ colour tables
 
 // Derive the FP32 colours, ln b (FP64 and FP32) and b minus its channel mean
-// from the FP64 colours.  The only place these tables are computed, so a state
-// restored from a checkpoint reproduces them bit for bit.
-__device__ void colour_tables(const Args& a) {
-    for (int i = 0; i < 3 * a.K; ++i) {
-        const double b = a.b64[i];
-        a.bf[i] = (float)b;
-        const double lg = log(b);
-        a.lnb64[i] = lg;
-        a.lnb[i] = (float)lg;
-    }
-    for (int k = 0; k < a.K; ++k) {
-        const float b0 = a.bf[3 * k], b1 = a.bf[3 * k + 1], b2 = a.bf[3 * k + 2];
+// from the FP64 colours, one wavefront with lane i owning colour entry i
+// (3K <= 48 < 64); bval is that lane's FP64 colour.  The only place these
+// tables are computed, so a state restored from a checkpoint reproduces them
+// bit for bit.
+__device__ void colour_tables_wave(const Args& a, int lane, double bval) {
+    const int nn = 3 * a.K;
+    const float bf = (float)bval;
+    const int k3 = 3 * (lane / 3);
+    const float b0 = __shfl(bf, k3, 64), b1 = __shfl(bf, k3 + 1, 64), b2 = __shfl(bf, k3 + 2, 64);
+    if (lane < nn) {
+        a.bf[lane] = bf;
+        const double lg = log(bval);
+        a.lnb64[lane] = lg;
+        a.lnb[lane] = (float)lg;
         const float mu = (b0 + b1 + b2) * (1.0f / 3.0f);
-        a.bcf[3 * k] = b0 - mu;
-        a.bcf[3 * k + 1] = b1 - mu;
-        a.bcf[3 * k + 2] = b2 - mu;
+        a.bcf[lane] = bf - mu;
     }
 }
 
 __device__ __forceinline__ void tables_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
-    if (threadIdx.x == 0) colour_tables(a);
+    const int lane = (int)threadIdx.x;
+    if (lane < 64) colour_tables_wave(a, lane, lane < 3 * a.K ? a.b64[lane] : 1.0);
 }
 
 // -------------------------------------------------------- base-colour solve
+
+// Eight wavefronts: enough to keep the partial loads in flight, and two per SIMD
+// leave the solving wavefront registers for a 48 x 48 factor without spilling.
+constexpr int BSOLVE_THREADS = 512;
 
 // One workgroup: reduce the per-workgroup sums, assemble the 3K x 3K system of
 // the base-colour step, solve it by FP64 Cholesky, apply the guards, update b.
@@ -795,17 +815,28 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
     double* sums = reinterpret_cast<double*>(smem);
     double (*Hm)[NN + 1] = reinterpret_cast<double (*)[NN + 1]>(smem + 8 * NS);
     double* gv = reinterpret_cast<double*>(smem + 8 * (NS + NN * (NN + 1)));
-    double* ysol = gv + NN;
-    double* dbsol = ysol + NN;
-    double& piv_ok = dbsol[NN];
     if (a.scal[S_BADIN] != 0.0) return;
     const double* part = a.partials + (long long)R_BS * a.part_stride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    for (int e = wave; e < NS; e += nw) {
-        double s = 0.0;
-        for (int b = lane; b < nb; b += 64) s += part[(long long)e * nb + b];
-        s = wave_sum(s);
-        if (lane == 0) sums[e] = s * (double)a.lam.data;
+    // eight sums per wavefront per round, so all their partial loads are in flight together
+    constexpr int U = 8;
+    for (int e0 = wave; e0 < NS; e0 += nw * U) {
+        double s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s[u] = 0.0;
+        for (int b = lane; b < nb; b += 64) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * nw;
+                if (e < NS) s[u] += part[(long long)e * nb + b];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double t = wave_sum(s[u]);
+            const int e = e0 + u * nw;
+            if (lane == 0 && e < NS) sums[e] = t * (double)a.lam.data;
+        }
     }
     __syncthreads();
     if (st.debug) {   // publish the raw sums for single-step access
@@ -860,63 +891,62 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
         }
     }
     __syncthreads();
-    // Cholesky H = L L^T in place (lower triangle), column by column
-    if (threadIdx.x == 0) {
-        double tr = 0.0;
-        for (int i2 = 0; i2 < NN; ++i2) tr += Hm[i2][i2];
-        piv_ok = tr;
-    }
-    __syncthreads();
-    const double trace = piv_ok;
-    __syncthreads();
-    if (threadIdx.x == 0) piv_ok = 1.0;
-    __syncthreads();
-    for (int jc = 0; jc < NN; ++jc) {
-        if (threadIdx.x == 0) {
-            double d = Hm[jc][jc];
-            for (int kk = 0; kk < jc; ++kk) d -= Hm[jc][kk] * Hm[jc][kk];
-            if (!(d > 1e-12 * trace)) { piv_ok = 0.0; d = 1.0; }
-            Hm[jc][jc] = sqrt(d);
-        }
-        __syncthreads();
-        const int i2 = jc + 1 + (int)threadIdx.x;
-        if (i2 < NN) {
-            double s = Hm[i2][jc];
-            for (int kk = 0; kk < jc; ++kk) s -= Hm[i2][kk] * Hm[jc][kk];
-            Hm[i2][jc] = s / Hm[jc][jc];
-        }
-        __syncthreads();
-    }
-    // forward and back substitution, one wavefront: lane i2 owns row i2 (NN <= 48)
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        for (int i2 = 0; i2 < NN; ++i2) {
-            if (lane == 0) {
-                double s = gv[i2];
-                for (int kk = 0; kk < i2; ++kk) s -= Hm[i2][kk] * ysol[kk];
-                ysol[i2] = s / Hm[i2][i2];
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        for (int i2 = NN - 1; i2 >= 0; --i2) {
-            if (lane == 0) {
-                double s = ysol[i2];
-                for (int kk = i2 + 1; kk < NN; ++kk) s -= Hm[kk][i2] * dbsol[kk];
-                dbsol[i2] = s / Hm[i2][i2];
-            }
-            __builtin_amdgcn_wave_barrier();
+    // H = L L^T and the two triangular solves on one wavefront, in registers:
+    // lane i holds row i of H (then of L) and entry i of the right-hand side;
+    // column values travel by readlane, so no step waits on LDS.
+    if (threadIdx.x >= 64) return;        // lane == threadIdx.x from here on
+    const bool act = lane < NN;
+    double h[NN];
+#pragma unroll
+    for (int k = 0; k < NN; ++k) h[k] = act ? Hm[lane][k] : 0.0;
+    double g = act ? gv[lane] : 0.0;
+    double trace = 0.0;
+#pragma unroll
+    for (int k = 0; k < NN; ++k) trace += Hm[k][k];
+    bool ok = true;
+    // right-looking Cholesky: column j, then the trailing lower triangle
+#pragma unroll
+    for (int j = 0; j < NN; ++j) {
+        double d = rdlane(h[j], j);
+        if (!(d > 1e-12 * trace)) { ok = false; d = 1.0; }
+        const double ljj = sqrt(d);
+        const double lij = h[j] / ljj;
+        h[j] = (lane == j) ? ljj : (lane > j ? lij : h[j]);
+#pragma unroll
+        for (int k = j + 1; k < NN; ++k) {
+            const double lkj = rdlane(lij, k);
+            if (lane >= k) h[k] -= lij * lkj;
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        bool ok = piv_ok != 0.0;
-        for (int i2 = 0; i2 < NN; ++i2) {
-            const double nb2 = a.b64[i2] + dbsol[i2];
-            if (!isfinite(nb2) || !(nb2 > 1e-4)) ok = false;
+    // L y = g
+#pragma unroll
+    for (int j = 0; j < NN; ++j) {
+        const double yj = rdlane(g, j) / rdlane(h[j], j);
+        g = (lane == j) ? yj : (lane > j ? g - h[j] * yj : g);
+    }
+    // L^T x = y  (L_ji lives in lane j's h[i])
+#pragma unroll
+    for (int j = NN - 1; j >= 0; --j) {
+        const double xj = rdlane(g, j) / rdlane(h[j], j);
+        double lji = 0.0;
+#pragma unroll
+        for (int i = 0; i < j; ++i) {
+            const double v = rdlane(h[i], j);
+            lji = (lane == i) ? v : lji;
         }
+        g = (lane == j) ? xj : (lane < j ? g - lji * xj : g);
+    }
+    // guards: a non-positive pivot, or a colour that would leave (1e-4, inf)
+    const double bold = act ? a.b64[lane] : 1.0;
+    const double bnew = bold + g;
+    const bool bad = act && (!isfinite(bnew) || !(bnew > 1e-4));
+    ok = ok && __ballot(bad) == 0;
+    if (ok) {
+        if (act) a.b64[lane] = bnew;
+        colour_tables_wave(a, lane, bnew);
+    }
+    if (lane == 0) {
         if (ok) {
-            for (int i2 = 0; i2 < NN; ++i2) a.b64[i2] += dbsol[i2];
-            colour_tables(a);
             a.scal[S_BACCEPT] = 1.0;
         } else {
             a.scal[S_BACCEPT] = 0.0;
@@ -1074,11 +1104,11 @@ constexpr size_t LDS_SMALL = 32;
 template <int K> constexpr size_t lds_gn_build() { return 32 + sizeof(float) * (K + 4) * HN; }
 template <int K> constexpr size_t lds_matvec() { return 32 + sizeof(float) * 2 * (K + 4) * HN; }
 template <int K> constexpr size_t lds_apply_bsum() {
-    return 32 + 6 * BS_BATCH * 8 + (NTHREADS / ((3 * K <= 32) ? 32 : 64)) * 3 * K * (K + 1) * 8 +
-           sizeof(float) * K * BS_BATCH;
+    return 32 + 6 * BS_STRIDE * 8 + (NTHREADS / ((3 * K <= 32) ? 32 : 64)) * 3 * K * (K + 1) * 8 +
+           sizeof(float) * K * BS_STRIDE;
 }
 template <int K> constexpr size_t lds_bsolve() {
-    return 8 * (3 * K * (K + 1) / 2 + 3 * K + 3 * K * (3 * K + 1) + 3 * 3 * K + 1);
+    return 8 * (3 * K * (K + 1) / 2 + 3 * K + 3 * K * (3 * K + 1) + 3 * K);
 }
 
 // ------------------------------------------------------------------ wrappers
@@ -1158,12 +1188,12 @@ __global__ __launch_bounds__(NTHREADS) void kb_scan(const Args* args, const int*
 
 // one workgroup per clip
 template <int K>
-__global__ __launch_bounds__(1024) void k_bsolve(Args a, Step st) {
+__global__ __launch_bounds__(BSOLVE_THREADS) void k_bsolve(Args a, Step st) {
     extern __shared__ __align__(16) char smem[];
     bsolve_body<K>(a, Lc{0, 1}, st, smem);
 }
 template <int KB>
-__global__ __launch_bounds__(1024) void kb_bsolve(const Args* args, Step st) {
+__global__ __launch_bounds__(BSOLVE_THREADS) void kb_bsolve(const Args* args, Step st) {
     extern __shared__ __align__(16) char smem[];
     const Args& a = args[blockIdx.x];
     dispatch_K<KB>(a.K, [&](auto kc) { bsolve_body<decltype(kc)::value>(a, Lc{0, 1}, st, smem); });
@@ -1235,7 +1265,7 @@ hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
             case KN_APPLY_BSUM:
                 hipLaunchKernelGGL(k_apply_bsum<KK>, dim3(a.nb_bs), blk, lds_apply_bsum<KK>(), s, a, st);
                 break;
-            case KN_BSOLVE: hipLaunchKernelGGL(k_bsolve<KK>, dim3(1), dim3(1024), lds_bsolve<KK>(), s, a, st); break;
+            case KN_BSOLVE: hipLaunchKernelGGL(k_bsolve<KK>, dim3(1), dim3(BSOLVE_THREADS), lds_bsolve<KK>(), s, a, st); break;
             case KN_ENERGY: hipLaunchKernelGGL(k_energy<KK>, grid, blk, LDS_SMALL, s, a, st); break;
             case KN_OUTPUT: hipLaunchKernelGGL(k_output<KK>, grid, blk, LDS_SMALL, s, a, st); break;
             default: break;
@@ -1277,7 +1307,7 @@ hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t 
                 hipLaunchKernelGGL(kb_apply_bsum<KB>, gbs, blk, lds_apply_bsum<KB>(), s, g.args, g.wg_bs, g.nclips, st);
                 break;
             case KN_BSOLVE:
-                hipLaunchKernelGGL(kb_bsolve<KB>, gone, dim3(1024), lds_bsolve<KB>(), s, g.args, st);
+                hipLaunchKernelGGL(kb_bsolve<KB>, gone, dim3(BSOLVE_THREADS), lds_bsolve<KB>(), s, g.args, st);
                 break;
             case KN_ENERGY:
                 hipLaunchKernelGGL(kb_energy<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
