@@ -102,15 +102,17 @@ def forward(p: dict, x: np.ndarray, rnd=bf16_round):
 
 def backward(p: dict, cache: dict, g_du: np.ndarray, g_db: np.ndarray, rnd=bf16_round) -> dict:
     """Gradients of a scalar loss with d(loss)/d(delta_u) = g_du and
-    d(loss)/d(delta_b) = g_db.  Rounding steps are treated as identity
-    (straight-through), as the GPU's backward does."""
+    d(loss)/d(delta_b) = g_db.  Rounding steps of the forward pass are treated
+    as identity (straight-through); the gradient tensors that are stored and fed
+    to the next contraction -- g_du and each layer's input gradient after the
+    ReLU mask -- are rounded by rnd where the GPU stores them in BF16."""
     acts, pre = cache["acts"], cache["pre"]
     g = {}
     g["hw"] = np.outer(g_db, cache["pooled"])
     g["hb"] = g_db.copy()
     H, W = acts[0].shape[1:]
     g_pool = p["hw"].T @ g_db                              # (32,)
-    gy = g_du
+    gy = rnd(g_du)
     for l in range(N_CONV - 1, -1, -1):
         gx, gw, gb = conv3x3_backward(acts[l], rnd(p[f"w{l}"]), gy)
         g[f"w{l}"], g[f"b{l}"] = gw, gb
@@ -119,7 +121,7 @@ def backward(p: dict, cache: dict, g_du: np.ndarray, g_db: np.ndarray, rnd=bf16_
         gx = gx.copy()
         if l == 5:
             gx += g_pool[:, None, None] / (H * W)          # the head reads the L5 features
-        gy = gx * (pre[l - 1] > 0.0)                        # through the ReLU of layer l-1
+        gy = rnd(gx * (pre[l - 1] > 0.0))                   # through the ReLU of layer l-1
     return g
 
 
