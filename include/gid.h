@@ -95,6 +95,10 @@ typedef struct {
     int32_t pcg_breakdowns;                     /* PCG stopped early by a breakdown guard */
     int32_t bstep_rejected;                     /* base-colour steps rejected by a guard */
     int32_t frame_index;                        /* 0 for the first frame of the clip */
+    int32_t warm_start_learned;                 /* 1 network start taken, 0 previous frame kept,
+                                                   -1 not evaluated (no network, or first frame) */
+    double energy_start_previous;               /* E at the previous frame's result (judge), else NaN */
+    double energy_start_learned;                /* E at the network's prediction (judge), else NaN */
 } gid_frame_stats;
 
 /* Fill *out with the paper's parameters for K base colours (Sec. 7) and the
@@ -244,6 +248,80 @@ int32_t gid_get_workgroups(const gid_ctx *ctx);
  * index).  With buf == NULL, *inout_bytes receives the required size. Synchronous. */
 gid_status gid_save_state(gid_ctx *ctx, void *buf, size_t *inout_bytes);
 gid_status gid_load_state(gid_ctx *ctx, const void *buf, size_t bytes);
+
+/* ---- learned warm start ----
+ * A network of six 3x3 convolutions (32 channels, ReLU after the first five,
+ * zero padding), BF16 weights and activations with FP32 accumulation on the
+ * matrix cores, predicting from the frame I_t and the previous unknowns
+ * u_{t-1} (3 + K + 4 input channels) the change du (K + 4 channels,
+ * u_t = u_{t-1} + du) and, through a linear head on the global average of the
+ * fifth layer's features, the change of the base colours db (3K).  It is this
+ * project's component, not the paper's (which names learned priors only as
+ * future work, Sec. 8).  The solver keeps judging it: see gid_set_warmstart.
+ *
+ * Parameters are one FP32 vector, in this order: for conv layer l = 0..5 its
+ * weights w[o][c][dy][dx] (c_out x c_in x 3 x 3 with c_in = K + 7 for l = 0
+ * and 32 otherwise, c_out = 32 except K + 4 for l = 5), then its bias b[c_out];
+ * then the head hw[3K][32] and hb[3K].  The caller provides the initial values
+ * (random numbers are drawn by the caller); the library keeps FP32 master
+ * weights, Adam moments and BF16 copies.  A network serves frames of exactly
+ * the width, height and K it was created for. */
+typedef struct gid_net gid_net;
+
+/* Number of parameters for K base colours, or -1 for K outside 1..16. */
+int64_t gid_net_num_params(int32_t K);
+
+/* Create a network and its workspace (activations of width x height pixels),
+ * enqueuing on hip_stream (NULL = null stream).  Parameters start at zero.
+ * Errors: GID_ERR_INVALID_ARG, GID_ERR_UNSUPPORTED (K + 7 > 32 input channels),
+ * GID_ERR_OUT_OF_MEMORY, GID_ERR_HIP. */
+gid_status gid_net_create(int32_t K, int32_t width, int32_t height, void *hip_stream, gid_net **out);
+gid_status gid_net_destroy(gid_net *net);
+
+/* Copy count (== gid_net_num_params(K)) FP32 parameters from host memory and
+ * reset the Adam state; get copies them back.  Synchronous. */
+gid_status gid_net_set_params(gid_net *net, const float *params_host, int64_t count);
+gid_status gid_net_get_params(gid_net *net, float *params_host, int64_t count);
+
+/* Inference: u_out = u_prev + du (K + 4 planes float32, device, planar like the
+ * solver's unknowns: r_0..r_2 log reflectance, T_0..T_K), db_out (3K float32,
+ * host, may be NULL; synchronous when given).  frame_dev: 3 planes float32. */
+gid_status gid_net_forward(gid_net *net, const float *frame_dev, const float *u_prev_dev, float *u_out_dev,
+                           float *db_out_host);
+
+/* Gradient of the loss 0.5 mean((du - du_target)^2) + 0.5 w_b mean((db - db_target)^2)
+ * with respect to every parameter (FP32, host, parameter layout) and the loss
+ * value; du_target: K + 4 planes (device), db_target: 3K float32 (host).
+ * The parameters are not changed.  Synchronous. */
+gid_status gid_net_gradients(gid_net *net, const float *frame_dev, const float *u_prev_dev,
+                             const float *du_target_dev, const float *db_target_host, float w_b,
+                             float *grad_host, double *loss_out);
+
+/* One training step: the gradient as above, then Adam (beta 0.9, 0.999,
+ * eps 1e-8, bias-corrected) with step size lr on the FP32 master weights.
+ * loss_out (may be NULL) receives the loss before the update (then synchronous). */
+gid_status gid_net_train_step(gid_net *net, const float *frame_dev, const float *u_prev_dev,
+                              const float *du_target_dev, const float *db_target_host, float w_b, float lr,
+                              double *loss_out);
+
+/* Single-layer access for verification: conv layer `layer` (0..5) applied to a
+ * width x height x 32 BF16 pixel-major input (device), out = conv + bias as
+ * width x height x 32 float32 (device); and its weight and bias gradients
+ * (host, layout of the layer's parameters) for input x and output gradient gy
+ * (both width x height x 32 BF16, device).  Synchronous. */
+gid_status gid_net_layer_forward(gid_net *net, int32_t layer, const void *in_dev, float *out_dev);
+gid_status gid_net_layer_wgrad(gid_net *net, int32_t layer, const void *x_dev, const void *gy_dev,
+                               float *gw_host, float *gb_host);
+const char *gid_net_last_error(const gid_net *net);
+
+/* Attach a network as the warm start of a solver context (NULL detaches).  On
+ * every frame after the first the solver evaluates the energy at the previous
+ * frame's result and at the network's prediction from it, keeps the lower as
+ * the start of the schedule (a prediction with a non-finite energy or a colour
+ * outside (1e-4, inf) is never kept) and reports both in gid_frame_stats.  The
+ * network must match the context's width, height and K and enqueue on the same
+ * stream.  Errors: GID_ERR_INVALID_ARG, GID_ERR_OUT_OF_MEMORY. */
+gid_status gid_set_warmstart(gid_ctx *ctx, gid_net *net);
 
 const char *gid_status_string(gid_status s);
 /* Last error message of this context (valid until its next call). */

@@ -4,8 +4,8 @@ The solve runs in libgid.so (HIP kernels behind the C ABI of include/gid.h);
 this package holds its sources (csrc/), the build script and a thin ctypes
 binding (gid.py).
 """
-from .gid import (Batch, GidError, GidFrameStats, GidParams, KERNEL_KINDS, LIB_PATH, SIGNATURES, Solver, TERMS,
+from .gid import (Batch, GidError, Net, GidFrameStats, GidParams, KERNEL_KINDS, LIB_PATH, SIGNATURES, Solver, TERMS,
                   default_params, load_library)
 
-__all__ = ["Batch", "GidError", "GidFrameStats", "GidParams", "KERNEL_KINDS", "LIB_PATH", "SIGNATURES", "Solver", "TERMS",
+__all__ = ["Batch", "GidError", "Net", "GidFrameStats", "GidParams", "KERNEL_KINDS", "LIB_PATH", "SIGNATURES", "Solver", "TERMS",
            "default_params", "load_library"]

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "gid_internal.h"
+#include "gid_net_internal.h"
 
 using namespace gid;
 
@@ -74,6 +75,12 @@ struct gid_ctx {
     int ev_used = 0;
     double kind_ms[GID_NUM_KERNEL_KINDS] = {};
     int64_t kind_n[GID_NUM_KERNEL_KINDS] = {};
+    // learned warm start
+    gid_net* wnet = nullptr;
+    void* warena = nullptr;
+    float *ucand = nullptr, *dbc = nullptr, *bfc = nullptr, *lnbc = nullptr, *bcfc = nullptr;
+    double *b64c = nullptr, *lnb64c = nullptr;
+    bool pend_judged = false;
     std::string err;
 };
 
@@ -205,6 +212,13 @@ Args base_args(const gid_ctx* c) {
     a.elog = c->elog;
     a.bsum = c->bsum;
     a.part_stride = c->part_stride;
+    a.ucand = c->ucand;
+    a.dbc = c->dbc;
+    a.b64c = c->b64c;
+    a.lnb64c = c->lnb64c;
+    a.bfc = c->bfc;
+    a.lnbc = c->lnbc;
+    a.bcfc = c->bcfc;
     return a;
 }
 
@@ -385,6 +399,8 @@ void release(gid_ctx* c) {
     if (c->h_elog) (void)hipHostFree(c->h_elog);
     if (c->h_b64) (void)hipHostFree(c->h_b64);
     if (c->h_small) (void)hipHostFree(c->h_small);
+    if (c->warena) (void)hipFree(c->warena);
+    c->warena = nullptr;
     c->arena = nullptr;
 }
 
@@ -565,6 +581,66 @@ static gid_status load_frame_impl(gid_ctx* c, const float* frame, const uint8_t*
     return GID_OK;
 }
 
+// The learned warm start's judge, between the frame's precompute and its
+// schedule: energy at the previous frame's result, the network's prediction
+// from it, energy at the prediction, then the device-side choice of the start.
+static gid_status enqueue_judge(gid_ctx* c, const Args& a) {
+    Step sp{};
+    sp.slot = JUDGE_PREV_SLOT;
+    GID_HIP(c, L1(c, c->stream, KN_ENERGY, a, sp));
+    GID_HIP(c, L1(c, c->stream, KN_ENERGY_FINISH, a, sp));
+    GID_HIP(c, gidnet_forward_dev(c->wnet, c->stream, c->I, c->u, c->ucand, c->dbc));
+    GID_HIP(c, L1(c, c->stream, KN_CAND_TABLES, a, Step{}));
+    Args ac = a;
+    ac.u = c->ucand;
+    ac.b64 = c->b64c;
+    ac.lnb64 = c->lnb64c;
+    ac.bf = c->bfc;
+    ac.lnb = c->lnbc;
+    ac.bcf = c->bcfc;
+    Step sn{};
+    sn.slot = JUDGE_NET_SLOT;
+    GID_HIP(c, L1(c, c->stream, KN_ENERGY, ac, sn));
+    GID_HIP(c, L1(c, c->stream, KN_ENERGY_FINISH, ac, sn));
+    GID_HIP(c, L1(c, c->stream, KN_JUDGE, a, Step{}));
+    return GID_OK;
+}
+
+gid_status gid_set_warmstart(gid_ctx* c, gid_net* net) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (!net) {
+        c->wnet = nullptr;
+        return GID_OK;
+    }
+    if (!gidnet_matches(net, c->K, c->W, c->H))
+        return fail(c, GID_ERR_INVALID_ARG, "the network's width, height and K must match the context's");
+    if (!c->warena) {
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 255) & ~(size_t)255;
+            return o;
+        };
+        const size_t o_u = take(sizeof(float) * (size_t)c->n * c->ps), o_db = take(sizeof(float) * 3 * KMAX);
+        const size_t o_b = take(sizeof(double) * 3 * KMAX), o_lb = take(sizeof(double) * 3 * KMAX);
+        const size_t o_bf = take(sizeof(float) * 3 * KMAX), o_lnb = take(sizeof(float) * 3 * KMAX),
+                     o_bc = take(sizeof(float) * 3 * KMAX);
+        char* base = nullptr;
+        if (hipMalloc(reinterpret_cast<void**>(&base), off) != hipSuccess)
+            return fail(c, GID_ERR_OUT_OF_MEMORY, "warm-start workspace");
+        c->warena = base;
+        c->ucand = reinterpret_cast<float*>(base + o_u);
+        c->dbc = reinterpret_cast<float*>(base + o_db);
+        c->b64c = reinterpret_cast<double*>(base + o_b);
+        c->lnb64c = reinterpret_cast<double*>(base + o_lb);
+        c->bfc = reinterpret_cast<float*>(base + o_bf);
+        c->lnbc = reinterpret_cast<float*>(base + o_lnb);
+        c->bcfc = reinterpret_cast<float*>(base + o_bc);
+    }
+    c->wnet = net;
+    return GID_OK;
+}
+
 gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* ids, float* layers,
                                double* b_out, gid_frame_stats* stats) {
     if (!c) return GID_ERR_INVALID_ARG;
@@ -573,6 +649,8 @@ gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* id
     if (s != GID_OK) return s;
     Args a;
     if ((s = load_frame_impl(c, frame, ids, a)) != GID_OK) return s;
+    const bool judged = c->wnet != nullptr && c->have_prev;
+    if (judged && (s = enqueue_judge(c, a)) != GID_OK) return s;
     const int mode = c->prm.refine_mode;
     const bool refine = mode == GID_REFINE_EVERY_STEP || (mode == GID_REFINE_FIRST_FRAME && c->frame_index == 0);
     const bool record = c->prm.record_energy != 0;
@@ -593,6 +671,7 @@ gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* id
     c->pend_frame = c->frame_index;
     c->pend_gn = c->prm.gn_iters;
     c->pend_had_prev = c->have_prev;
+    c->pend_judged = judged;
     c->frame_index += 1;
     c->have_prev = true;
     return GID_OK;
@@ -626,6 +705,10 @@ gid_status gid_synchronize(gid_ctx* c) {
         st->pcg_breakdowns = (int32_t)c->h_scal[S_BREAKDOWNS];
         st->bstep_rejected = (int32_t)c->h_scal[S_BREJECT];
         st->frame_index = c->pend_frame;
+        st->warm_start_learned = c->pend_judged ? (c->h_scal[S_LEARNED] != 0.0 ? 1 : 0) : -1;
+        st->energy_start_previous =
+            c->pend_judged ? c->h_elog[(long long)JUDGE_PREV_SLOT * ELOG_STRIDE] : std::nan("");
+        st->energy_start_learned = c->pend_judged ? c->h_elog[(long long)JUDGE_NET_SLOT * ELOG_STRIDE] : std::nan("");
     }
     if (!std::isfinite(fin[0])) return fail(c, GID_ERR_NUMERIC, "final energy is not finite");
     return GID_OK;
@@ -975,6 +1058,8 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
                                float* const* layers) {
     if (!b || !frames || !ids) return bfail(b, GID_ERR_INVALID_ARG, "frames and ids are required");
     if (b->pending) return bfail(b, GID_ERR_STATE, "synchronize the previous batch step first");
+    for (gid_ctx* c : b->clips)
+        if (c->wnet) return bfail(b, GID_ERR_UNSUPPORTED, "batched clips run without a learned warm start");
     const int n = (int)b->clips.size();
     std::vector<int> act;
     unsigned long long mask = 0;

@@ -18,7 +18,9 @@ constexpr int NTHREADS = TX * TYW;
 constexpr int KMAX = 16;
 constexpr int NTERMS = GID_NUM_TERMS;
 constexpr int ELOG_STRIDE = 1 + NTERMS;   // total + terms per energy slot
-constexpr int ELOG_SLOTS = GID_MAX_HALF_STEPS + 2;
+constexpr int ELOG_SLOTS = GID_MAX_HALF_STEPS + 4;
+constexpr int JUDGE_PREV_SLOT = ELOG_SLOTS - 4;    // warm-start judge: energy at the previous frame's result
+constexpr int JUDGE_NET_SLOT = ELOG_SLOTS - 3;     // warm-start judge: energy at the network's prediction
 
 // Slots of the device scalar array (doubles).
 enum Scal : int {
@@ -27,6 +29,8 @@ enum Scal : int {
     S_BREJECT,      // count of rejected base-colour steps this frame
     S_BACCEPT,      // 1 if the last base-colour step was accepted
     S_BADIN,        // non-finite frame values or out-of-range ids in this frame's input
+    S_CAND_OK,      // 1 if the network's colour prediction is admissible (every component in (1e-4, inf))
+    S_LEARNED,      // 1 if the judge kept the network's prediction as this frame's start
     S_RZ_LOG,       // first of 64 slots: final <r, z> of each layer step
     NSCAL = S_RZ_LOG + 64
 };
@@ -96,6 +100,14 @@ struct Args {
     float* out2;             // second caller output (debug diag)
     const float* pdebug;     // caller p (debug apply)
     long long part_stride;   // doubles per reduction site
+    // learned warm start (null unless a network is attached)
+    float* ucand;            // n planes: the network's prediction
+    float* dbc;              // 3K predicted colour change (FP32)
+    double* b64c;            // K x 3 candidate colours and their tables
+    double* lnb64c;
+    float* bfc;
+    float* lnbc;
+    float* bcfc;
 };
 
 // Number of base-colour step sums: 3 K(K+1)/2 Gram entries + 3K right-hand side entries.
@@ -103,7 +115,7 @@ __host__ __device__ inline int bstep_nsums(int K) { return 3 * K * (K + 1) / 2 +
 
 enum Kern : int {
     KN_RESET = 0, KN_SCAN, KN_PRECOMPUTE, KN_GN_BUILD, KN_MATVEC, KN_UPDATE, KN_APPLY_BSUM, KN_BSOLVE,
-    KN_ENERGY, KN_ENERGY_FINISH, KN_OUTPUT, KN_TABLES
+    KN_ENERGY, KN_ENERGY_FINISH, KN_OUTPUT, KN_TABLES, KN_CAND_TABLES, KN_JUDGE
 };
 
 // A batched launch over several clips: per-clip descriptors in device memory and

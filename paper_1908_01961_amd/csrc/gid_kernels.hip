@@ -778,24 +778,68 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
 // (3K <= 48 < 64); bval is that lane's FP64 colour.  The only place these
 // tables are computed, so a state restored from a checkpoint reproduces them
 // bit for bit.
-__device__ void colour_tables_wave(const Args& a, int lane, double bval) {
-    const int nn = 3 * a.K;
+__device__ void colour_tables_to(int K, int lane, double bval, float* bfo, double* lnb64o, float* lnbo, float* bcfo) {
+    const int nn = 3 * K;
     const float bf = (float)bval;
     const int k3 = 3 * (lane / 3);
     const float b0 = __shfl(bf, k3, 64), b1 = __shfl(bf, k3 + 1, 64), b2 = __shfl(bf, k3 + 2, 64);
     if (lane < nn) {
-        a.bf[lane] = bf;
+        bfo[lane] = bf;
         const double lg = log(bval);
-        a.lnb64[lane] = lg;
-        a.lnb[lane] = (float)lg;
+        lnb64o[lane] = lg;
+        lnbo[lane] = (float)lg;
         const float mu = (b0 + b1 + b2) * (1.0f / 3.0f);
-        a.bcf[lane] = bf - mu;
+        bcfo[lane] = bf - mu;
     }
+}
+
+__device__ __forceinline__ void colour_tables_wave(const Args& a, int lane, double bval) {
+    colour_tables_to(a.K, lane, bval, a.bf, a.lnb64, a.lnb, a.bcf);
 }
 
 __device__ __forceinline__ void tables_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     const int lane = (int)threadIdx.x;
     if (lane < 64) colour_tables_wave(a, lane, lane < 3 * a.K ? a.b64[lane] : 1.0);
+}
+
+// ------------------------------------------------- learned warm-start judge
+
+// Candidate colours b + db from the network's head and their tables; flags
+// whether every component is admissible.  One wavefront.
+__device__ __forceinline__ void cand_tables_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+    const int lane = (int)threadIdx.x;
+    if (lane >= 64) return;
+    const bool act = lane < 3 * a.K;
+    const double bval = act ? a.b64[lane] + (double)a.dbc[lane] : 1.0;
+    const bool bad = act && (!isfinite(bval) || !(bval > 1e-4));
+    const bool ok = __ballot(bad) == 0;
+    if (act) a.b64c[lane] = bval;
+    colour_tables_to(a.K, lane, ok ? bval : 1.0, a.bfc, a.lnb64c, a.lnbc, a.bcfc);
+    if (lane == 0) a.scal[S_CAND_OK] = ok ? 1.0 : 0.0;
+}
+
+// Keep the network's prediction as the frame's start when its energy is finite
+// and lower than the energy at the previous frame's result (and its colours are
+// admissible); otherwise leave the state alone.  Every workgroup takes the same
+// decision from the two logged totals and copies its own pixels.
+__device__ __forceinline__ void judge_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+    const double e_prev = a.elog[(long long)JUDGE_PREV_SLOT * ELOG_STRIDE];
+    const double e_net = a.elog[(long long)JUDGE_NET_SLOT * ELOG_STRIDE];
+    const bool use = a.scal[S_BADIN] == 0.0 && a.scal[S_CAND_OK] != 0.0 && isfinite(e_net) && e_net < e_prev;
+    if (lead_thread(lc)) a.scal[S_LEARNED] = use ? 1.0 : 0.0;
+    if (!use) return;
+    const int n = a.K + 4;
+    const long long ps = a.ps;
+    for_each_pixel(a, lc, [&](int x, int y, long long i) {
+        for (int v = 0; v < n; ++v) a.u[v * ps + i] = a.ucand[v * ps + i];
+    });
+    if (lc.lb == 0 && threadIdx.x < 64) {
+        const int lane = (int)threadIdx.x;
+        const bool act = lane < 3 * a.K;
+        const double bval = act ? a.b64c[lane] : 1.0;
+        if (act) a.b64[lane] = bval;
+        colour_tables_wave(a, lane, bval);
+    }
 }
 
 // -------------------------------------------------------- base-colour solve
@@ -1208,6 +1252,8 @@ __global__ __launch_bounds__(NTHREADS) void kb_energy_finish(const Args* args, S
 }
 __global__ void k_reset_frame(Args a, Step st) { reset_frame_body(a, Lc{0, 1}, st, nullptr); }
 __global__ void k_tables(Args a, Step st) { tables_body(a, Lc{0, 1}, st, nullptr); }
+__global__ void k_cand_tables(Args a, Step st) { cand_tables_body(a, Lc{0, 1}, st, nullptr); }
+__global__ __launch_bounds__(NTHREADS) void k_judge(Args a, Step st) { judge_body(a, whole_grid(), st, nullptr); }
 __global__ void kb_reset_frame(const Args* args, Step st) { reset_frame_body(args[blockIdx.x], Lc{0, 1}, st, nullptr); }
 
 }  // namespace
@@ -1248,6 +1294,12 @@ hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
             return hipGetLastError();
         case KN_ENERGY_FINISH:
             hipLaunchKernelGGL(k_energy_finish, dim3(1), blk, LDS_SMALL, s, a, st);
+            return hipGetLastError();
+        case KN_CAND_TABLES:
+            hipLaunchKernelGGL(k_cand_tables, dim3(1), dim3(64), 0, s, a, st);
+            return hipGetLastError();
+        case KN_JUDGE:
+            hipLaunchKernelGGL(k_judge, dim3(a.nblocks), dim3(NTHREADS), 0, s, a, st);
             return hipGetLastError();
         case KN_TABLES:
             hipLaunchKernelGGL(k_tables, dim3(1), dim3(64), 0, s, a, st);

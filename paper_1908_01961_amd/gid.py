@@ -44,7 +44,8 @@ class GidFrameStats(ctypes.Structure):
     _fields_ = [("energy_final", c_double), ("energy_terms", c_double * 8),
                 ("energy_half", c_double * MAX_HALF), ("pcg_rz_last", c_double * 64),
                 ("n_half", c_int32), ("gn_done", c_int32), ("pcg_breakdowns", c_int32),
-                ("bstep_rejected", c_int32), ("frame_index", c_int32)]
+                ("bstep_rejected", c_int32), ("frame_index", c_int32), ("warm_start_learned", c_int32),
+                ("energy_start_previous", c_double), ("energy_start_learned", c_double)]
 
     def to_dict(self) -> dict:
         return dict(energy_final=self.energy_final,
@@ -52,7 +53,10 @@ class GidFrameStats(ctypes.Structure):
                     energy_half=list(self.energy_half[: self.n_half]),
                     pcg_rz_last=list(self.pcg_rz_last[: self.gn_done]),
                     gn_done=self.gn_done, pcg_breakdowns=self.pcg_breakdowns,
-                    bstep_rejected=self.bstep_rejected, frame_index=self.frame_index)
+                    bstep_rejected=self.bstep_rejected, frame_index=self.frame_index,
+                    warm_start_learned=self.warm_start_learned,
+                    energy_start_previous=self.energy_start_previous,
+                    energy_start_learned=self.energy_start_learned)
 
 
 _lib = None
@@ -89,6 +93,20 @@ SIGNATURES = [
     ("gid_get_workgroups", c_int32, [c_void_p]),
     ("gid_save_state", c_int32, [c_void_p, c_void_p, POINTER(c_size_t)]),
     ("gid_load_state", c_int32, [c_void_p, c_void_p, c_size_t]),
+    ("gid_net_num_params", ctypes.c_int64, [c_int32]),
+    ("gid_net_create", c_int32, [c_int32, c_int32, c_int32, c_void_p, POINTER(c_void_p)]),
+    ("gid_net_destroy", c_int32, [c_void_p]),
+    ("gid_net_set_params", c_int32, [c_void_p, POINTER(c_float), ctypes.c_int64]),
+    ("gid_net_get_params", c_int32, [c_void_p, POINTER(c_float), ctypes.c_int64]),
+    ("gid_net_forward", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_float)]),
+    ("gid_net_gradients", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_float), c_float,
+                                    POINTER(c_float), POINTER(c_double)]),
+    ("gid_net_train_step", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_float), c_float, c_float,
+                                     POINTER(c_double)]),
+    ("gid_net_layer_forward", c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    ("gid_net_layer_wgrad", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_float), POINTER(c_float)]),
+    ("gid_net_last_error", ctypes.c_char_p, [c_void_p]),
+    ("gid_set_warmstart", c_int32, [c_void_p, c_void_p]),
     ("gid_status_string", ctypes.c_char_p, [c_int32]),
     ("gid_last_error", ctypes.c_char_p, [c_void_p]),
 ]
@@ -181,6 +199,11 @@ class Solver:
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.gid_destroy(self.h)
             self.h = None
+
+    def set_warmstart(self, net: "Net | None"):
+        """Attach (or with None detach) a learned warm-start network."""
+        self._check(self.lib.gid_set_warmstart(self.h, net.h if net is not None else None), "gid_set_warmstart")
+        self._net = net
 
     def __del__(self):
         try:
@@ -319,6 +342,106 @@ class Solver:
     def load_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._check(self.lib.gid_load_state(self.h, buf, len(blob)), "gid_load_state")
+
+
+def _f32(arr, n, name):
+    a = np.ascontiguousarray(np.asarray(arr, np.float32).reshape(-1))
+    if a.size != n:
+        raise ValueError(f"{name} must have {n} values, got {a.size}")
+    return a, a.ctypes.data_as(POINTER(c_float))
+
+
+class Net:
+    """The learned warm-start network for frames of width x height with K base colours."""
+
+    def __init__(self, K: int, width: int, height: int, stream=None):
+        import torch
+        self.lib = load_library()
+        self.K, self.W, self.H = int(K), int(width), int(height)
+        self.n = self.K + 4
+        self.nparam = int(self.lib.gid_net_num_params(self.K))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        h = c_void_p()
+        st = self.lib.gid_net_create(self.K, self.W, self.H, c_void_p(stream.cuda_stream), byref(h))
+        if st != GID_OK:
+            raise GidError(st, f"gid_net_create(K={self.K}, {self.W}x{self.H})")
+        self.h = h
+
+    def _check(self, st, what):
+        if st != GID_OK:
+            raise GidError(st, f"{what}: {self.lib.gid_net_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.gid_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        a, p = _f32(flat, self.nparam, "params")
+        self._check(self.lib.gid_net_set_params(self.h, p, self.nparam), "gid_net_set_params")
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.nparam, np.float32)
+        self._check(self.lib.gid_net_get_params(self.h, out.ctypes.data_as(POINTER(c_float)), self.nparam),
+                    "gid_net_get_params")
+        return out
+
+    def forward(self, frame, u_prev, u_out):
+        import torch
+        f = _ptr(frame, torch.float32, (3, self.H, self.W), "frame")
+        u = _ptr(u_prev, torch.float32, (self.n, self.H, self.W), "u_prev")
+        o = _ptr(u_out, torch.float32, (self.n, self.H, self.W), "u_out")
+        db = np.zeros(3 * self.K, np.float32)
+        self._check(self.lib.gid_net_forward(self.h, f, u, o, db.ctypes.data_as(POINTER(c_float))),
+                    "gid_net_forward")
+        return db
+
+    def gradients(self, frame, u_prev, du_target, db_target, w_b: float = 1.0):
+        import torch
+        f = _ptr(frame, torch.float32, (3, self.H, self.W), "frame")
+        u = _ptr(u_prev, torch.float32, (self.n, self.H, self.W), "u_prev")
+        t = _ptr(du_target, torch.float32, (self.n, self.H, self.W), "du_target")
+        tdb, tp = _f32(db_target, 3 * self.K, "db_target")
+        g = np.zeros(self.nparam, np.float32)
+        loss = c_double()
+        self._check(self.lib.gid_net_gradients(self.h, f, u, t, tp, float(w_b), g.ctypes.data_as(POINTER(c_float)),
+                                               byref(loss)), "gid_net_gradients")
+        return g, loss.value
+
+    def train_step(self, frame, u_prev, du_target, db_target, lr: float, w_b: float = 1.0, want_loss=True):
+        import torch
+        f = _ptr(frame, torch.float32, (3, self.H, self.W), "frame")
+        u = _ptr(u_prev, torch.float32, (self.n, self.H, self.W), "u_prev")
+        t = _ptr(du_target, torch.float32, (self.n, self.H, self.W), "du_target")
+        tdb, tp = _f32(db_target, 3 * self.K, "db_target")
+        loss = c_double()
+        self._check(self.lib.gid_net_train_step(self.h, f, u, t, tp, float(w_b), float(lr),
+                                                byref(loss) if want_loss else None), "gid_net_train_step")
+        return loss.value if want_loss else None
+
+    def layer_forward(self, layer: int, x_nhwc, out_nhwc):
+        import torch
+        x = _ptr(x_nhwc, torch.bfloat16, (self.H, self.W, 32), "x")
+        o = _ptr(out_nhwc, torch.float32, (self.H, self.W, 32), "out")
+        self._check(self.lib.gid_net_layer_forward(self.h, int(layer), x, o), "gid_net_layer_forward")
+
+    def layer_wgrad(self, layer: int, x_nhwc, gy_nhwc, cin: int, cout: int):
+        import torch
+        x = _ptr(x_nhwc, torch.bfloat16, (self.H, self.W, 32), "x")
+        gy = _ptr(gy_nhwc, torch.bfloat16, (self.H, self.W, 32), "gy")
+        gw = np.zeros(cout * cin * 9, np.float32)
+        gb = np.zeros(cout, np.float32)
+        self._check(self.lib.gid_net_layer_wgrad(self.h, int(layer), x, gy, gw.ctypes.data_as(POINTER(c_float)),
+                                                 gb.ctypes.data_as(POINTER(c_float))), "gid_net_layer_wgrad")
+        return gw.reshape(cout, cin, 3, 3), gb
 
 
 class Batch:

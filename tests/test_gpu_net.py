@@ -1,0 +1,243 @@
+"""The learned warm-start network on the GPU versus its FP64 reference, through the C ABI.
+
+Single layers are fed BF16 values, so every product is exact in FP32 and the
+only difference to the FP64 reference is the FP32 summation: 2e-5 of the
+output's largest magnitude.  The whole network rounds every stored activation
+(and, in the backward pass, every stored gradient) to BF16 on both sides; a
+value whose FP32 and FP64 sums fall on different sides of a BF16 rounding
+boundary moves by one BF16 step (2^-8 relative), so whole-network outputs and
+gradients are compared by relative Frobenius norm.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.warmstart as WS
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*m):
+    print("[gpu-case]", *m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_01961_amd as G
+    G.load_library()
+    return _t
+
+
+def _layers(K):
+    n = K + 4
+    cin = [3 + n] + [32] * 5
+    cout = [32] * 5 + [n]
+    return n, cin, cout
+
+
+def dict_to_flat(p, K):
+    """The parameter vector in the library's documented order."""
+    parts = []
+    for l in range(WS.N_CONV):
+        parts += [p[f"w{l}"].ravel(), p[f"b{l}"].ravel()]
+    parts += [p["hw"].ravel(), p["hb"].ravel()]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def flat_to_dict(flat, K):
+    n, cin, cout = _layers(K)
+    p, o = {}, 0
+    for l in range(WS.N_CONV):
+        m = cout[l] * cin[l] * 9
+        p[f"w{l}"] = flat[o:o + m].reshape(cout[l], cin[l], 3, 3).astype(np.float64)
+        o += m
+        p[f"b{l}"] = flat[o:o + cout[l]].astype(np.float64)
+        o += cout[l]
+    p["hw"] = flat[o:o + 3 * K * 32].reshape(3 * K, 32).astype(np.float64)
+    o += 3 * K * 32
+    p["hb"] = flat[o:o + 3 * K].astype(np.float64)
+    return p
+
+
+def _random_params(K, seed, scale_last=1.0):
+    """He-scaled random parameters with a live output layer and head (FP32 values)."""
+    rng = np.random.default_rng(seed)
+    n, cin, cout = _layers(K)
+    p = {}
+    for l in range(WS.N_CONV):
+        std = np.sqrt(2.0 / (9 * cin[l])) * (scale_last if l == WS.N_CONV - 1 else 1.0)
+        p[f"w{l}"] = rng.normal(0.0, std, size=(cout[l], cin[l], 3, 3))
+        p[f"b{l}"] = rng.normal(0.0, 0.05, size=cout[l])
+    p["hw"] = rng.normal(0.0, 0.2, size=(3 * K, 32))
+    p["hb"] = rng.normal(0.0, 0.02, size=3 * K)
+    flat = dict_to_flat(p, K)
+    return flat, flat_to_dict(flat, K)
+
+
+def _inputs(K, W, H, seed):
+    rng = np.random.default_rng(seed)
+    n = K + 4
+    frame = rng.uniform(0.05, 0.95, size=(3, H, W)).astype(np.float32)
+    u = np.empty((n, H, W), np.float32)
+    u[:3] = rng.uniform(-1.5, -0.1, size=(3, H, W))
+    u[3] = rng.uniform(0.3, 1.0, size=(H, W))
+    u[4:] = rng.uniform(-0.02, 0.1, size=(K, H, W))
+    return frame, u
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(1e-30, np.linalg.norm(b)))
+
+
+# ---------------------------------------------------------------- single layers
+
+@pytest.mark.parametrize("layer", [0, 2, 5])
+def test_layer_forward_matches_reference(torch, layer):
+    import paper_1908_01961_amd as G
+    K, W, H = 4, 70, 9                      # a ragged 64-pixel strip and a ragged 4-row group
+    n, cin, cout = _layers(K)
+    flat, p = _random_params(K, 10 + layer)
+    net = G.Net(K, W, H)
+    net.set_params(flat)
+    rng = np.random.default_rng(20 + layer)
+    x = np.zeros((H, W, 32), np.float32)
+    x[:, :, :cin[layer]] = rng.normal(0, 1, size=(H, W, cin[layer]))
+    xb = torch.from_numpy(x).to(torch.bfloat16).cuda()
+    out = torch.empty((H, W, 32), dtype=torch.float32, device="cuda")
+    net.layer_forward(layer, xb, out)
+    xr = xb.float().cpu().numpy().astype(np.float64).transpose(2, 0, 1)[:cin[layer]]
+    ref = WS.conv3x3(xr, WS.bf16_round(p[f"w{layer}"]), p[f"b{layer}"])          # (cout, H, W)
+    got = out.cpu().numpy().transpose(2, 0, 1)[:cout[layer]]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _say(f"layer {layer} forward: max err / max |ref| = {err:.2e}")
+    assert err <= 2e-5
+    net.close()
+
+
+@pytest.mark.parametrize("layer", [0, 3, 5])
+def test_layer_weight_gradient_matches_reference(torch, layer):
+    import paper_1908_01961_amd as G
+    K, W, H = 4, 70, 9
+    n, cin, cout = _layers(K)
+    flat, _ = _random_params(K, 30)
+    net = G.Net(K, W, H)
+    net.set_params(flat)
+    rng = np.random.default_rng(40 + layer)
+    x = np.zeros((H, W, 32), np.float32)
+    x[:, :, :cin[layer]] = rng.normal(0, 1, size=(H, W, cin[layer]))
+    gy = np.zeros((H, W, 32), np.float32)
+    gy[:, :, :cout[layer]] = rng.normal(0, 1, size=(H, W, cout[layer]))
+    xb = torch.from_numpy(x).to(torch.bfloat16).cuda()
+    gb_ = torch.from_numpy(gy).to(torch.bfloat16).cuda()
+    gw, gb = net.layer_wgrad(layer, xb, gb_, cin[layer], cout[layer])
+    xr = xb.float().cpu().numpy().astype(np.float64).transpose(2, 0, 1)[:cin[layer]]
+    gr = gb_.float().cpu().numpy().astype(np.float64).transpose(2, 0, 1)[:cout[layer]]
+    _, gw_ref, gb_ref = WS.conv3x3_backward(xr, np.zeros((cout[layer], cin[layer], 3, 3)), gr)
+    ew = np.abs(gw - gw_ref).max() / np.abs(gw_ref).max()
+    eb = np.abs(gb - gb_ref).max() / np.abs(gb_ref).max()
+    _say(f"layer {layer} wgrad: weights {ew:.2e}, bias {eb:.2e}")
+    assert ew <= 2e-5 and eb <= 2e-5
+    net.close()
+
+
+# ---------------------------------------------------------------- whole network
+
+CASE = dict(K=4, W=80, H=24)
+
+
+def test_forward_matches_reference(torch):
+    import paper_1908_01961_amd as G
+    K, W, H = CASE["K"], CASE["W"], CASE["H"]
+    flat, p = _random_params(K, 50)
+    frame, u = _inputs(K, W, H, 51)
+    net = G.Net(K, W, H)
+    net.set_params(flat)
+    uo = torch.empty((K + 4, H, W), dtype=torch.float32, device="cuda")
+    db = net.forward(_dev(torch, frame), _dev(torch, u), uo)
+    du = uo.cpu().numpy().astype(np.float64) - u
+    x = np.concatenate([frame, u]).astype(np.float64)
+    du_ref, db_ref, _ = WS.forward(p, x)
+    e_u, e_b = _rel(du, du_ref), _rel(db, db_ref)
+    _say(f"forward: |du - ref| / |ref| = {e_u:.2e}, |db - ref| / |ref| = {e_b:.2e}, "
+         f"max |du - ref| = {np.abs(du - du_ref).max():.2e} (max |ref| {np.abs(du_ref).max():.2e})")
+    assert e_u <= 5e-3 and e_b <= 5e-3
+    net.close()
+
+
+def test_gradients_match_reference(torch):
+    import paper_1908_01961_amd as G
+    K, W, H = CASE["K"], CASE["W"], CASE["H"]
+    flat, p = _random_params(K, 60)
+    frame, u = _inputs(K, W, H, 61)
+    rng = np.random.default_rng(62)
+    du_t = (0.05 * rng.normal(size=u.shape)).astype(np.float32)
+    db_t = (0.05 * rng.normal(size=3 * K)).astype(np.float32)
+    wb = 2.0
+    net = G.Net(K, W, H)
+    net.set_params(flat)
+    g, loss = net.gradients(_dev(torch, frame), _dev(torch, u), _dev(torch, du_t), db_t, wb)
+    gd = flat_to_dict(g, K)
+    x = np.concatenate([frame, u]).astype(np.float64)
+    du, dbv, cache = WS.forward(p, x)
+    loss_ref, g_du, g_db = WS.mse_loss(du, dbv, du_t.astype(np.float64), db_t.astype(np.float64), wb)
+    gref = WS.backward(p, cache, g_du, g_db)
+    _say(f"loss gpu {loss:.8e} ref {loss_ref:.8e}")
+    assert loss == pytest.approx(loss_ref, rel=5e-3)
+    for k in gref:
+        e = _rel(gd[k], gref[k])
+        _say(f"  grad {k}: rel {e:.2e} (|ref| {np.linalg.norm(gref[k]):.2e})")
+        assert e <= 2e-2, k
+    net.close()
+
+
+def test_adam_step_matches_reference(torch):
+    import paper_1908_01961_amd as G
+    K, W, H = CASE["K"], CASE["W"], CASE["H"]
+    flat, p = _random_params(K, 70)
+    frame, u = _inputs(K, W, H, 71)
+    rng = np.random.default_rng(72)
+    du_t = (0.05 * rng.normal(size=u.shape)).astype(np.float32)
+    db_t = (0.05 * rng.normal(size=3 * K)).astype(np.float32)
+    lr = 1e-3
+    net = G.Net(K, W, H)
+    net.set_params(flat)
+    g, _ = net.gradients(_dev(torch, frame), _dev(torch, u), _dev(torch, du_t), db_t, 1.0)
+    net.train_step(_dev(torch, frame), _dev(torch, u), _dev(torch, du_t), db_t, lr)
+    after = net.get_params()
+    # reference Adam step from the GPU's own gradient: checks the update rule alone
+    pd = {k: v.copy() for k, v in flat_to_dict(flat, K).items()}
+    gd = flat_to_dict(g, K)
+    m = {k: np.zeros_like(v) for k, v in pd.items()}
+    v = {k: np.zeros_like(v) for k, v in pd.items()}
+    WS.adam_step(pd, gd, m, v, 1, lr)
+    ref = dict_to_flat(pd, K).astype(np.float64)
+    err = np.abs(after - ref).max()
+    _say(f"adam: max |p_gpu - p_ref| = {err:.2e} (step size {lr})")
+    assert err <= 1e-6
+    net.close()
+
+
+def test_training_reduces_the_loss(torch):
+    import paper_1908_01961_amd as G
+    K, W, H = CASE["K"], CASE["W"], CASE["H"]
+    flat, _ = _random_params(K, 80, scale_last=0.1)
+    frame, u = _inputs(K, W, H, 81)
+    # a target the network can represent: a smooth function of the input
+    du_t = (0.1 * np.tanh(u - u.mean(axis=(1, 2), keepdims=True))).astype(np.float32)
+    db_t = np.full(3 * K, 0.02, np.float32)
+    net = G.Net(K, W, H)
+    net.set_params(flat)
+    f, uu, t = _dev(torch, frame), _dev(torch, u), _dev(torch, du_t)
+    losses = [net.train_step(f, uu, t, db_t, 2e-3) for _ in range(60)]
+    _say(f"training: loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.3 * losses[0]
+    net.close()
