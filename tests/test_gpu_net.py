@@ -1,12 +1,13 @@
 """The learned warm-start network on the GPU versus its FP64 reference, through the C ABI.
 
 Single layers are fed BF16 values, so every product is exact in FP32 and the
-only difference to the FP64 reference is the FP32 summation: 2e-5 of the
-output's largest magnitude.  The whole network rounds every stored activation
+only difference to the FP64 reference is the FP32 summation: 2e-6 of the
+output's largest magnitude (measured ~2e-7).  The whole network rounds every stored activation
 (and, in the backward pass, every stored gradient) to BF16 on both sides; a
 value whose FP32 and FP64 sums fall on different sides of a BF16 rounding
 boundary moves by one BF16 step (2^-8 relative), so whole-network outputs and
-gradients are compared by relative Frobenius norm.
+gradients are compared by relative Frobenius norm (measured on the 80 x 24
+case: du 9e-4, db 7e-6, gradients at most 3e-4; the bars below are about 3x).
 """
 import sys
 
@@ -119,7 +120,7 @@ def test_layer_forward_matches_reference(torch, layer):
     got = out.cpu().numpy().transpose(2, 0, 1)[:cout[layer]]
     err = np.abs(got - ref).max() / np.abs(ref).max()
     _say(f"layer {layer} forward: max err / max |ref| = {err:.2e}")
-    assert err <= 2e-5
+    assert err <= 2e-6
     net.close()
 
 
@@ -145,7 +146,7 @@ def test_layer_weight_gradient_matches_reference(torch, layer):
     ew = np.abs(gw - gw_ref).max() / np.abs(gw_ref).max()
     eb = np.abs(gb - gb_ref).max() / np.abs(gb_ref).max()
     _say(f"layer {layer} wgrad: weights {ew:.2e}, bias {eb:.2e}")
-    assert ew <= 2e-5 and eb <= 2e-5
+    assert ew <= 2e-6 and eb <= 2e-6
     net.close()
 
 
@@ -169,7 +170,7 @@ def test_forward_matches_reference(torch):
     e_u, e_b = _rel(du, du_ref), _rel(db, db_ref)
     _say(f"forward: |du - ref| / |ref| = {e_u:.2e}, |db - ref| / |ref| = {e_b:.2e}, "
          f"max |du - ref| = {np.abs(du - du_ref).max():.2e} (max |ref| {np.abs(du_ref).max():.2e})")
-    assert e_u <= 5e-3 and e_b <= 5e-3
+    assert e_u <= 3e-3 and e_b <= 3e-5
     net.close()
 
 
@@ -191,11 +192,11 @@ def test_gradients_match_reference(torch):
     loss_ref, g_du, g_db = WS.mse_loss(du, dbv, du_t.astype(np.float64), db_t.astype(np.float64), wb)
     gref = WS.backward(p, cache, g_du, g_db)
     _say(f"loss gpu {loss:.8e} ref {loss_ref:.8e}")
-    assert loss == pytest.approx(loss_ref, rel=5e-3)
+    assert loss == pytest.approx(loss_ref, rel=1e-5)
     for k in gref:
         e = _rel(gd[k], gref[k])
         _say(f"  grad {k}: rel {e:.2e} (|ref| {np.linalg.norm(gref[k]):.2e})")
-        assert e <= 2e-2, k
+        assert e <= 1e-3, k
     net.close()
 
 
