@@ -29,6 +29,8 @@ struct gid_net {
     long long nwaves = 0;
     float *pooled = nullptr, *db = nullptr, *tdb = nullptr, *addc = nullptr;
     double *loss_db = nullptr, *loss_tot = nullptr;
+    double* stage = nullptr;
+    int nstage = 0;
     float *gw_part = nullptr, *gb_part = nullptr;
     int nparts = 0;
     float* h_db = nullptr;
@@ -108,6 +110,8 @@ hipError_t forward_trunk(gid_net* net, hipStream_t s, const float* frame, const 
     HeadArgs h{};
     h.pool_part = net->pool_part;
     h.nparts = net->nwaves;
+    h.stage = net->stage;
+    h.nstage = net->nstage;
     h.npix = (double)net->ps;
     h.K = net->K;
     h.hw = net->P + net->hwoff;
@@ -138,6 +142,8 @@ hipError_t train_pass(gid_net* net, const float* frame, const float* u, const fl
     HeadArgs h{};
     h.pool_part = net->pool_part;
     h.nparts = net->nwaves;
+    h.stage = net->stage;
+    h.nstage = net->nstage;
     h.npix = (double)net->ps;
     h.K = net->K;
     h.hw = net->P + net->hwoff;
@@ -248,6 +254,8 @@ gid_status gid_net_create(int32_t K, int32_t width, int32_t height, void* hip_st
     const size_t o_lp = take(8 * (size_t)net->nwaves);
     const size_t o_pooled = take(4 * C), o_db = take(4 * 3 * K), o_tdb = take(4 * 3 * K), o_addc = take(4 * C);
     const size_t o_ldb = take(8), o_ltot = take(8);
+    net->nstage = (int)std::max<long long>(1, std::min<long long>(POOL_STAGES, net->nwaves));
+    const size_t o_stage = take(8 * (size_t)net->nstage * C);
     const size_t o_gw = take(4 * (size_t)net->nparts * 9 * C * C), o_gb = take(4 * (size_t)net->nparts * C);
     char* base = nullptr;
     if (hipMalloc(reinterpret_cast<void**>(&base), off) != hipSuccess) {
@@ -273,6 +281,7 @@ gid_status gid_net_create(int32_t K, int32_t width, int32_t height, void* hip_st
     net->addc = reinterpret_cast<float*>(base + o_addc);
     net->loss_db = reinterpret_cast<double*>(base + o_ldb);
     net->loss_tot = reinterpret_cast<double*>(base + o_ltot);
+    net->stage = reinterpret_cast<double*>(base + o_stage);
     net->gw_part = reinterpret_cast<float*>(base + o_gw);
     net->gb_part = reinterpret_cast<float*>(base + o_gb);
     if (hipMemsetAsync(base, 0, off, net->stream) != hipSuccess ||

@@ -17,6 +17,7 @@ constexpr int STRIP = 64;          // pixels of one row handled by a wavefront
 constexpr int CONV_ROWS = 4;       // rows (wavefronts) per workgroup
 constexpr int CONV_THREADS = 64 * CONV_ROWS;
 constexpr int HEAD_THREADS = 256;
+constexpr int CONV_GRID_MAX = 1 << 20;  // conv grid cap (one tile per workgroup below it: measured faster than a resident grid)
 
 enum ConvMode { M_RELU = 0, M_ADD = 1, M_LOSS = 2, M_MASK = 3, M_RAW = 4 };
 
@@ -46,9 +47,13 @@ struct WgradArgs {
     float* gb_part;          // [parts][32]
 };
 
+constexpr int POOL_STAGES = 120;    // workgroups of the first pooling stage
+
 struct HeadArgs {
     const float* pool_part;  // [nparts][32]
     long long nparts;
+    double* stage;           // [nstage][32] first-stage sums
+    int nstage;
     double npix;
     int K;
     const float* hw;         // [3K][32]

@@ -14,7 +14,8 @@
 //   B (32 x 16):  lane l holds k = 8 (l / 16) + j, column l % 16
 //   D (16 x 16):  lane l holds rows 4 (l / 16) + i, i = 0..3, column l % 16
 // A wavefront covers a strip of 64 pixels of one row (four M blocks) and keeps
-// the whole layer's B fragments (9 taps x N blocks) in registers.
+// the whole layer's B fragments (9 taps x N blocks) in registers; the four
+// wavefronts of a workgroup share an LDS copy of their input rows.
 //
 // Reductions (pooling, loss, weight gradients) are deterministic: every
 // wavefront or workgroup writes its own partial, a consumer sums them in index
@@ -55,104 +56,158 @@ __device__ __forceinline__ double wave_sum64(double v) {
 
 // ------------------------------------------------------------ convolution
 
-template <int NB>
+// The workgroup's four rows (one per wavefront) read a 6-row x 66-pixel halo
+// tile of the input, staged once in LDS with coalesced 16-byte loads; every
+// A fragment is then one conflict-free 128-bit LDS read (16 lanes cover 16
+// consecutive pixels = 1 KiB).  MODE selects the epilogue at compile time.
+constexpr int TROWS = CONV_ROWS + 2, TCOLS = STRIP + 2;
+
+template <int NB, int MODE>
 __global__ __launch_bounds__(CONV_THREADS) void k_conv(ConvArgs a) {
+    __shared__ __align__(16) __bf16 tile[TROWS][TCOLS][C];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int y = blockIdx.y * CONV_ROWS + wv, x0 = blockIdx.x * STRIP;
-    const long long wave_id = ((long long)blockIdx.y * gridDim.x + blockIdx.x) * CONV_ROWS + wv;
+    const long long wave_id = (long long)blockIdx.x * CONV_ROWS + wv;
     const int W = a.W, H = a.H;
-    const bool rowin = y < H;
+    const int nsx = (W + STRIP - 1) / STRIP, nsy = (H + CONV_ROWS - 1) / CONV_ROWS;
     bf16x8 bw[9][NB];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) bw[t][nb] = load8(a.w + ((t * C + nb * 16 + r16) * C + 8 * kq));
-    f32x4 acc[4][NB];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    if (rowin) {
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const int yy = y + dy - 1;
-            const bool rok = yy >= 0 && yy < H;
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int xx = x0 + 16 * m + r16 + dx - 1;
-                    const bf16x8 av = (rok && xx >= 0 && xx < W)
-                                          ? load8(a.in + ((long long)yy * W + xx) * C + 8 * kq)
-                                          : zero8();
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-                        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[dy * 3 + dx][nb], acc[m][nb],
-                                                                             0, 0, 0);
-                }
-            }
-        }
-    }
-    // epilogue: pixel x0 + 16 m + 4 kq + i, channel 16 nb + r16
     float pool[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) pool[nb] = 0.0f;
     double lacc = 0.0;
+    // tiles of 4 rows x 64 pixels; above CONV_GRID_MAX tiles a workgroup takes several
+    for (int tl = blockIdx.x; tl < nsx * nsy; tl += gridDim.x) {
+        const int y0 = (tl / nsx) * CONV_ROWS, x0 = (tl % nsx) * STRIP;
+        const int y = y0 + wv;
+        const bool rowin = y < H;
+        __syncthreads();    // the previous tile's epilogue is done with the LDS
+        for (int e = threadIdx.x; e < TROWS * TCOLS * 4; e += CONV_THREADS) {
+            const int q = e & 3, col = (e >> 2) % TCOLS, row = (e >> 2) / TCOLS;
+            const int yy = y0 + row - 1, xx = x0 + col - 1;
+            const bf16x8 v = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                                 ? load8(a.in + ((long long)yy * W + xx) * C + 8 * q)
+                                 : zero8();
+            *reinterpret_cast<bf16x8*>(&tile[row][col][8 * q]) = v;
+        }
+        f32x4 acc[4][NB];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int xp = x0 + 16 * m + 4 * kq + i;
-            if (!rowin || xp >= W) continue;
-            const long long px = (long long)y * W + xp;
+            for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        __syncthreads();
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int o = 16 * nb + r16;
-                const float v = acc[m][nb][i];
-                switch (a.mode) {
-                    case M_RELU: {
-                        const __bf16 r = (__bf16)fmaxf(v + a.bias[o], 0.0f);
-                        a.out_b[px * C + o] = r;
-                        pool[nb] += (float)r;
-                        break;
-                    }
-                    case M_ADD:
-                        if (o < a.nout) a.out_f[o * a.ps + px] = a.uprev[o * a.ps + px] + (v + a.bias[o]);
-                        break;
-                    case M_LOSS: {
-                        float g = 0.0f;
-                        if (o < a.nout) {
-                            const float e = (v + a.bias[o]) - a.tgt[o * a.ps + px];
-                            g = e * a.gscale;
-                            lacc += (double)e * (double)e;
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[wv + dy][16 * m + r16 + dx][8 * kq]);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[dy * 3 + dx][nb], acc[m][nb], 0, 0, 0);
+                }
+        // epilogue: pixel x0 + 16 m + 4 kq + i, channel 16 nb + r16
+        constexpr bool NHWC_OUT = MODE == M_RELU || MODE == M_LOSS || MODE == M_MASK;
+        if constexpr (NHWC_OUT) {
+            // values to BF16 in this wavefront's 64 x 32 block of the (no longer needed)
+            // input tile, then each lane stores one pixel's 64 bytes with four 16-byte stores
+            static_assert(NB == 2, "pixel-major outputs carry all 32 channels");
+            __syncthreads();
+            __bf16* blk = &tile[0][0][0] + wv * STRIP * C;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int lp = 16 * m + 4 * kq + i, xp = x0 + lp;
+                    const bool in = rowin && xp < W;
+                    const long long px = (long long)y * W + xp;
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const int o = 16 * nb + r16;
+                        const float v = acc[m][nb][i];
+                        __bf16 r;
+                        if constexpr (MODE == M_RELU) {
+                            r = (__bf16)fmaxf(v + a.bias[o], 0.0f);
+                            if (in) pool[nb] += (float)r;
+                        } else if constexpr (MODE == M_LOSS) {
+                            float g = 0.0f;
+                            if (in && o < a.nout) {
+                                const float e = (v + a.bias[o]) - a.tgt[o * a.ps + px];
+                                g = e * a.gscale;
+                                lacc += (double)e * (double)e;
+                            }
+                            r = (__bf16)g;
+                        } else {
+                            const float sv = v + (a.addc ? a.addc[o] : 0.0f);
+                            r = (__bf16)((in && (float)a.mask[px * C + o] > 0.0f) ? sv : 0.0f);
                         }
-                        a.out_b[px * C + o] = (__bf16)g;
-                        break;
+                        blk[lp * C + o] = r;
                     }
-                    case M_MASK: {
-                        const float s = v + (a.addc ? a.addc[o] : 0.0f);
-                        a.out_b[px * C + o] = (__bf16)((float)a.mask[px * C + o] > 0.0f ? s : 0.0f);
-                        break;
+                }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int xp = x0 + lane;
+            if (rowin && xp < W) {
+                const long long px = (long long)y * W + xp;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    *reinterpret_cast<bf16x8*>(a.out_b + px * C + 8 * q) =
+                        *reinterpret_cast<const bf16x8*>(blk + lane * C + 8 * q);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const int o = 16 * nb + r16;
+                    const int xb = x0 + 16 * m + 4 * kq;
+                    if (!rowin) continue;
+                    const long long pb = (long long)y * W + xb;
+                    if constexpr (MODE == M_ADD) {
+                        if (o >= a.nout) continue;
+                        const float bo = a.bias[o];
+                        if ((W & 3) == 0 && xb + 3 < W) {
+                            const float4 up = *reinterpret_cast<const float4*>(a.uprev + o * a.ps + pb);
+                            float4 r;
+                            r.x = up.x + (acc[m][nb][0] + bo);
+                            r.y = up.y + (acc[m][nb][1] + bo);
+                            r.z = up.z + (acc[m][nb][2] + bo);
+                            r.w = up.w + (acc[m][nb][3] + bo);
+                            *reinterpret_cast<float4*>(a.out_f + o * a.ps + pb) = r;
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (xb + i < W) a.out_f[o * a.ps + pb + i] = a.uprev[o * a.ps + pb + i] + (acc[m][nb][i] + bo);
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (xb + i < W) a.out_f[(pb + i) * C + o] = acc[m][nb][i] + a.bias[o];
                     }
-                    default:   // M_RAW
-                        a.out_f[px * C + o] = v + a.bias[o];
-                        break;
                 }
             }
         }
     }
-    if (a.mode == M_RELU && a.pool_part) {
+    if constexpr (MODE == M_RELU) {
+        if (a.pool_part) {
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const float s = col_sum(pool[nb]);
-            if (kq == 0) a.pool_part[wave_id * C + 16 * nb + r16] = s;
+            for (int nb = 0; nb < NB; ++nb) {
+                const float s = col_sum(pool[nb]);
+                if (kq == 0) a.pool_part[wave_id * C + 16 * nb + r16] = s;
+            }
+            if (NB == 1 && kq == 0) a.pool_part[wave_id * C + 16 + r16] = 0.0f;
         }
-        if (NB == 1 && kq == 0) a.pool_part[wave_id * C + 16 + r16] = 0.0f;
     }
-    if (a.mode == M_LOSS && a.loss_part) {
-        const double s = wave_sum64(lacc);
-        if (lane == 0) a.loss_part[wave_id] = s;
+    if constexpr (MODE == M_LOSS) {
+        if (a.loss_part) {
+            const double s = wave_sum64(lacc);
+            if (lane == 0) a.loss_part[wave_id] = s;
+        }
     }
 }
 
@@ -246,6 +301,25 @@ __global__ void k_wgrad_reduce(const float* gw_part, const float* gb_part, int n
 
 // ------------------------------------------------------------ head, loss
 
+// First stage of the global average pool: workgroup g sums its contiguous range
+// of the per-wavefront channel sums (FP64, fixed order) into stage[g][32].
+__global__ __launch_bounds__(HEAD_THREADS) void k_pool_stage(const float* pool_part, long long nparts, int ngroups,
+                                                            double* stage) {
+    __shared__ double part[HEAD_THREADS];
+    const int t = threadIdx.x, c = t % C, sub = t / C;
+    constexpr int NSUB = HEAD_THREADS / C;
+    const long long w0 = nparts * blockIdx.x / ngroups, w1 = nparts * (blockIdx.x + 1) / ngroups;
+    double s = 0.0;
+    for (long long w = w0 + sub; w < w1; w += NSUB) s += (double)pool_part[w * C + c];
+    part[t] = s;
+    __syncthreads();
+    if (t < C) {
+        double tot = 0.0;
+        for (int k = 0; k < NSUB; ++k) tot += part[k * C + t];
+        stage[(long long)blockIdx.x * C + t] = tot;
+    }
+}
+
 // Global average pool of the layer-5 features and the linear colour head
 // db = hw pooled + hb.  With train != 0 also the head's gradients for the loss
 // 0.5 w_b mean((db - t_db)^2), the pooled-feature gradient spread over the
@@ -258,7 +332,7 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_head(HeadArgs a) {
     const int c = t % C, g = t / C;
     constexpr int NGRP = HEAD_THREADS / C;
     double s = 0.0;
-    for (long long w = g; w < a.nparts; w += NGRP) s += (double)a.pool_part[w * C + c];
+    for (int w = g; w < a.nstage; w += NGRP) s += a.stage[(long long)w * C + c];
     part[t] = s;
     __syncthreads();
     if (t < C) {
@@ -366,16 +440,29 @@ __global__ void k_adam(float* p, float* m, float* v, const float* g, long long n
 
 // ------------------------------------------------------------ launchers
 
+int conv_grid(int W, int H) {
+    const long long tiles = (long long)((W + STRIP - 1) / STRIP) * ((H + CONV_ROWS - 1) / CONV_ROWS);
+    return (int)(tiles < CONV_GRID_MAX ? tiles : CONV_GRID_MAX);
+}
+
 hipError_t launch_conv(const ConvArgs& a, int nb, hipStream_t s) {
-    const dim3 grid((a.W + STRIP - 1) / STRIP, (a.H + CONV_ROWS - 1) / CONV_ROWS), blk(CONV_THREADS);
-    if (nb == 1) hipLaunchKernelGGL(k_conv<1>, grid, blk, 0, s, a);
-    else hipLaunchKernelGGL(k_conv<2>, grid, blk, 0, s, a);
+    const dim3 grid(conv_grid(a.W, a.H)), blk(CONV_THREADS);
+    // one output block only where nothing reads channels 16..31 of the output
+    if (nb == 1 && a.mode != M_ADD) return hipErrorInvalidValue;
+    switch (a.mode) {
+        case M_RELU: hipLaunchKernelGGL((k_conv<2, M_RELU>), grid, blk, 0, s, a); break;
+        case M_ADD:
+            if (nb == 1) hipLaunchKernelGGL((k_conv<1, M_ADD>), grid, blk, 0, s, a);
+            else hipLaunchKernelGGL((k_conv<2, M_ADD>), grid, blk, 0, s, a);
+            break;
+        case M_LOSS: hipLaunchKernelGGL((k_conv<2, M_LOSS>), grid, blk, 0, s, a); break;
+        case M_MASK: hipLaunchKernelGGL((k_conv<2, M_MASK>), grid, blk, 0, s, a); break;
+        default: hipLaunchKernelGGL((k_conv<2, M_RAW>), grid, blk, 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
-long long conv_waves(int W, int H) {
-    return (long long)((W + STRIP - 1) / STRIP) * ((H + CONV_ROWS - 1) / CONV_ROWS) * CONV_ROWS;
-}
+long long conv_waves(int W, int H) { return (long long)conv_grid(W, H) * CONV_ROWS; }
 
 hipError_t launch_wgrad(const WgradArgs& a, int nparts, int cin, int cout, float* grad_w, float* grad_b,
                         hipStream_t s) {
@@ -387,6 +474,8 @@ hipError_t launch_wgrad(const WgradArgs& a, int nparts, int cin, int cout, float
 }
 
 hipError_t launch_head(const HeadArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool_stage, dim3(a.nstage), dim3(HEAD_THREADS), 0, s, a.pool_part, a.nparts, a.nstage,
+                       a.stage);
     hipLaunchKernelGGL(k_head, dim3(1), dim3(HEAD_THREADS), 0, s, a);
     return hipGetLastError();
 }

@@ -1,0 +1,117 @@
+"""Training and use of the learned warm start (library calls only).
+
+The network (include/gid.h, gid_net_*) learns the solver's own frame-to-frame
+update: from the frame I_t and the previous result u_{t-1} it predicts
+du = u_t - u_{t-1} and db = b_t - b_{t-1}, where (u_t, b_t) is what the plain
+schedule produces for frame t from (u_{t-1}, b_{t-1}).  Training pairs come
+from decomposing seeded synthetic clips with the GPU solver; the network is
+trained on the GPU by its own forward, backward and Adam kernels.  The network
+is fully convolutional with a global-average colour head, so weights trained at
+one frame size serve any other (copied into a network created for that size).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from .gid import Net, Solver, default_params
+
+C_HID = 32
+N_CONV = 6
+
+
+def layer_shapes(K: int):
+    """(c_in, c_out) of the six conv layers for K base colours."""
+    n = K + 4
+    return [(3 + n, C_HID)] + [(C_HID, C_HID)] * 4 + [(C_HID, n)]
+
+
+def init_params(K: int, seed: int) -> np.ndarray:
+    """He-normal conv weights and zero biases, with the output layer and the
+    colour head at zero so the untrained network predicts no change (the judge
+    then keeps the previous frame).  Layout of include/gid.h."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for l, (ci, co) in enumerate(layer_shapes(K)):
+        if l < N_CONV - 1:
+            w = rng.normal(0.0, np.sqrt(2.0 / (9 * ci)), size=(co, ci, 3, 3))
+        else:
+            w = np.zeros((co, ci, 3, 3))
+        parts += [w.ravel(), np.zeros(co)]
+    parts += [np.zeros(3 * K * C_HID), np.zeros(3 * K)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+class PairStore:
+    """Training pairs resident in device memory: (frame_t, u_{t-1}, du_t, db_t)."""
+
+    def __init__(self):
+        self.frames, self.u_prev, self.du, self.db = [], [], [], []
+
+    def __len__(self):
+        return len(self.frames)
+
+    def add_clip(self, clip, G: int, P: int, temporal: bool = True):
+        """Decompose the clip with the plain schedule and keep a pair per frame t >= 1."""
+        import torch
+        W, H, K = clip.width, clip.height, clip.K
+        s = Solver(W, H, default_params(K, gn_iters=G, pcg_iters=P, temporal=int(temporal)))
+        s.set_base_colors(clip.b_init)
+        prev_u, prev_b = None, None
+        frames = torch.from_numpy(np.ascontiguousarray(clip.frames)).cuda()
+        ids = torch.from_numpy(np.ascontiguousarray(clip.ids)).cuda()
+        for t in range(clip.nframes):
+            b, _ = s.decompose_frame(frames[t], ids[t])
+            u, _ = s.get_state()
+            if prev_u is not None:
+                self.frames.append(frames[t].clone())
+                self.u_prev.append(prev_u)
+                self.du.append(u - prev_u)
+                self.db.append((np.asarray(b) - prev_b).astype(np.float32).reshape(-1))
+            prev_u, prev_b = u, np.asarray(b).copy()
+        s.close()
+
+
+def make_training_set(K: int, W: int, H: int, nframes: int, frames_per_clip: int, G: int, P: int,
+                      seed0: int, log=None) -> PairStore:
+    """nframes pairs from seeded synthetic clips (seeds seed0, seed0 + 1, ...)."""
+    from scenes import make_clip
+    store = PairStore()
+    i = 0
+    while len(store) < nframes:
+        clip = make_clip(W, H, K, frames_per_clip, seed0 + i)
+        store.add_clip(clip, G, P)
+        i += 1
+        if log:
+            log(f"training clip {i}: {len(store)} pairs")
+    for name in ("frames", "u_prev", "du", "db"):
+        setattr(store, name, getattr(store, name)[:nframes])
+    return store
+
+
+def train(net: Net, store: PairStore, epochs: int, lr: float, w_b: float = 1.0, seed: int = 0, log=None):
+    """Adam over the stored pairs in a seeded shuffled order; returns the mean loss per epoch."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(len(store))
+        tot = 0.0
+        t0 = time.perf_counter()
+        for j, k in enumerate(order):
+            want = j % 50 == 0
+            loss = net.train_step(store.frames[k], store.u_prev[k], store.du[k], store.db[k], lr, w_b,
+                                  want_loss=want)
+            if want:
+                tot += loss
+        hist.append(tot / max(1, (len(order) + 49) // 50))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: mean sampled loss {hist[-1]:.4e} ({time.perf_counter() - t0:.1f} s)")
+    return hist
+
+
+def transfer(net_from: Net, K: int, W: int, H: int) -> Net:
+    """A network for frames of W x H with the trained weights of net_from."""
+    net = Net(K, W, H)
+    net.set_params(net_from.get_params())
+    return net
