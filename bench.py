@@ -70,6 +70,110 @@ def cpu_baseline(clip, G, P, frames):
                 host_cpus=os.cpu_count(), host_affinity=len(os.sched_getaffinity(0)))
 
 
+def learned_vs_plain(clip, w, train_frames: int, log):
+    """The learned warm start against the plain method on the same clip.
+
+    Frame 0 (no previous frame to warm-start from) runs the plain schedule and
+    is checkpointed; every candidate then solves frames 1..F-1 from that
+    checkpoint.  The network is trained first (untimed) on train_frames pairs
+    from plain decompositions of synthetic clips with seeds disjoint from the
+    workload's.  A schedule counts as matched when on every frame its final
+    energy is at most the plain method's times (1 + 1e-4).  Timed passes run
+    the frames back to back on the device; energies come from a separate pass
+    with per-frame statistics."""
+    import numpy as np
+    import torch
+
+    import paper_1908_01961_amd as G
+    from paper_1908_01961_amd import warmstart as WSP
+
+    W_, H_, K, F = clip.width, clip.height, clip.K, clip.nframes
+    Gp, Pp = w["G"], w["P"]
+    frames = torch.from_numpy(clip.frames).cuda()
+    ids = torch.from_numpy(clip.ids).cuda()
+
+    def ctx(g, p):
+        return G.Solver(W_, H_, G.default_params(K, gn_iters=g, pcg_iters=p, temporal=1, refine_mode="every",
+                                                 record_energy=0, use_graph=1))
+
+    s0 = ctx(Gp, Pp)
+    s0.set_base_colors(clip.b_init)
+    s0.decompose_frame(frames[0], ids[0])
+    blob = s0.save_state()
+    s0.close()
+
+    def run(g, p, net=None):
+        s = ctx(g, p)
+        s.load_state(blob)
+        if net is not None:
+            s.set_warmstart(net)
+        E, taken = [], 0
+        for t in range(1, F):
+            _, st = s.decompose_frame(frames[t], ids[t])
+            E.append(st["energy_final"])
+            taken += st["warm_start_learned"] == 1
+        best = None
+        for _ in range(3):
+            s.load_state(blob)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for t in range(1, F):
+                s.decompose_frame_async(frames[t], ids[t])
+            s.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        s.close()
+        return np.array(E), best, taken
+
+    px = (F - 1) * W_ * H_
+    E_plain, t_plain, _ = run(Gp, Pp)
+    log(f"plain {Gp}x{Pp}: {px / t_plain / 1e6:.1f} Mpx/s on frames 1..{F - 1}")
+    t0 = time.perf_counter()
+    f = 2
+    while (W_ // f) * (H_ // f) > 80000:
+        f += 1
+    tw, th = max(64, W_ // f), max(32, H_ // f)       # training frames: the workload's aspect, ~77k pixels
+    store = WSP.make_training_set(K, tw, th, train_frames, 41, Gp, Pp, 10000)
+    net_t = G.Net(K, tw, th)
+    net_t.set_params(WSP.init_params(K, 1))
+    hist = WSP.train(net_t, store, epochs=4, lr=1e-3)
+    del store
+    net = WSP.transfer(net_t, K, W_, H_)
+    net_t.close()
+    train_s = time.perf_counter() - t0
+    log(f"network trained on {train_frames} pairs at {tw}x{th} in {train_s:.1f} s (loss {hist[-1]:.3e})")
+
+    def summary(E, dt, taken=None):
+        ex = E / E_plain - 1.0
+        d = dict(mpx_s=round(px / dt / 1e6, 2), frames_s=round((F - 1) / dt, 1),
+                 energy_excess_max=float(ex.max()), energy_excess_median=float(np.median(ex)),
+                 matched=bool(ex.max() <= 1e-4))
+        if taken is not None:
+            d["learned_start_taken"] = f"{taken}/{F - 1}"
+        return d
+
+    scheds = []
+    for g, p in ((1, Pp), (2, Pp), (Gp, Pp)):
+        E_l, t_l, taken = run(g, p, net)
+        row = dict(schedule=f"{g}x{p}", learned=summary(E_l, t_l, taken))
+        if (g, p) != (Gp, Pp):
+            E_r, t_r, _ = run(g, p)
+            row["plain_same_schedule"] = summary(E_r, t_r)
+        scheds.append(row)
+        log(f"learned {g}x{p}: {row['learned']}")
+    net.close()
+    plain_mpx = px / t_plain / 1e6
+    matched = [r for r in scheds if r["learned"]["matched"]]
+    best = max(matched, key=lambda r: r["learned"]["mpx_s"]) if matched else None
+    return dict(frames_timed=F - 1, plain=dict(schedule=f"{Gp}x{Pp}", mpx_s=round(plain_mpx, 2)),
+                train=dict(pairs=train_frames, size=f"{tw}x{th}", seconds=round(train_s, 1), final_loss=hist[-1],
+                           seeds="10000 and up"),
+                schedules=scheds,
+                criterion="E_learned[t] <= E_plain[t] * (1 + 1e-4) for every frame t >= 1",
+                best_matched_schedule=best["schedule"] if best else None,
+                speedup_at_matched_energy=round(best["learned"]["mpx_s"] / plain_mpx, 3) if best else None)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +183,9 @@ def main() -> int:
     ap.add_argument("--frames", type=int, default=None, help="frames per clip (default: the workload's)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of graph replay")
     ap.add_argument("--cpu-frames", type=int, default=3, help="oracle sample size in frames (0: skip)")
+    ap.add_argument("--learned", choices=("on", "off"), default="on",
+                    help="also compare the learned warm start with the plain method on the workload")
+    ap.add_argument("--train-frames", type=int, default=2000, help="training pairs for the learned warm start")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device 5 times: a plain copy "
                          "of known size for scaling hardware byte counters (0: skip)")
@@ -156,6 +263,11 @@ def main() -> int:
                        share=round(v["ms"] / max(1e-12, sum(x["ms"] for x in kt.values())), 4))
                for k, v in kt.items() if v["launches"]}
 
+    learned = None
+    if args.learned == "on":
+        learned = learned_vs_plain(clip, w, args.train_frames,
+                                   lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+
     cpu = None
     if args.cpu_frames > 0:
         print(f"[bench] oracle on {args.cpu_frames} frame(s)", file=sys.stderr, flush=True)
@@ -179,6 +291,7 @@ def main() -> int:
                    "refine": "every", "method": "plain", "graph": not args.no_graph},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned_vs_plain": learned,
         "frame_roofline": dict(achieved=round(frame_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                                frac=round(frame_gbs / HBM_PEAK_GBS, 4),
                                algorithmic_bytes_per_frame=ab["frame"] * W_ * H_),
