@@ -17,7 +17,6 @@ constexpr int STRIP = 64;          // pixels of one row handled by a wavefront
 constexpr int CONV_ROWS = 4;       // rows (wavefronts) per workgroup
 constexpr int CONV_THREADS = 64 * CONV_ROWS;
 constexpr int HEAD_THREADS = 256;
-constexpr int CONV_GRID_MAX = 1 << 20;  // conv grid cap (one tile per workgroup below it: measured faster than a resident grid)
 
 enum ConvMode { M_RELU = 0, M_ADD = 1, M_LOSS = 2, M_MASK = 3, M_RAW = 4 };
 

@@ -67,9 +67,20 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(ConvArgs a) {
     __shared__ __align__(16) __bf16 tile[TROWS][TCOLS][C];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, kq = lane >> 4;
-    const long long wave_id = (long long)blockIdx.x * CONV_ROWS + wv;
     const int W = a.W, H = a.H;
-    const int nsx = (W + STRIP - 1) / STRIP, nsy = (H + CONV_ROWS - 1) / CONV_ROWS;
+    const int nsx = (W + STRIP - 1) / STRIP;
+    const long long wave_id = (long long)blockIdx.x * CONV_ROWS + wv;
+    const int y0 = ((int)blockIdx.x / nsx) * CONV_ROWS, x0 = ((int)blockIdx.x % nsx) * STRIP;
+    const int y = y0 + wv;
+    const bool rowin = y < H;
+    for (int e = threadIdx.x; e < TROWS * TCOLS * 4; e += CONV_THREADS) {
+        const int q = e & 3, col = (e >> 2) % TCOLS, row = (e >> 2) / TCOLS;
+        const int yy = y0 + row - 1, xx = x0 + col - 1;
+        const bf16x8 v = (yy >= 0 && yy < H && xx >= 0 && xx < W)
+                             ? load8(a.in + ((long long)yy * W + xx) * C + 8 * q)
+                             : zero8();
+        *reinterpret_cast<bf16x8*>(&tile[row][col][8 * q]) = v;
+    }
     bf16x8 bw[9][NB];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
@@ -79,116 +90,101 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(ConvArgs a) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) pool[nb] = 0.0f;
     double lacc = 0.0;
-    // tiles of 4 rows x 64 pixels; above CONV_GRID_MAX tiles a workgroup takes several
-    for (int tl = blockIdx.x; tl < nsx * nsy; tl += gridDim.x) {
-        const int y0 = (tl / nsx) * CONV_ROWS, x0 = (tl % nsx) * STRIP;
-        const int y = y0 + wv;
-        const bool rowin = y < H;
-        __syncthreads();    // the previous tile's epilogue is done with the LDS
-        for (int e = threadIdx.x; e < TROWS * TCOLS * 4; e += CONV_THREADS) {
-            const int q = e & 3, col = (e >> 2) % TCOLS, row = (e >> 2) / TCOLS;
-            const int yy = y0 + row - 1, xx = x0 + col - 1;
-            const bf16x8 v = (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                                 ? load8(a.in + ((long long)yy * W + xx) * C + 8 * q)
-                                 : zero8();
-            *reinterpret_cast<bf16x8*>(&tile[row][col][8 * q]) = v;
-        }
-        f32x4 acc[4][NB];
+    f32x4 acc[4][NB];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    __syncthreads();
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[wv + dy][16 * m + r16 + dx][8 * kq]);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[dy * 3 + dx][nb], acc[m][nb], 0, 0, 0);
+            }
+    // epilogue: pixel x0 + 16 m + 4 kq + i, channel 16 nb + r16
+    constexpr bool NHWC_OUT = MODE == M_RELU || MODE == M_LOSS || MODE == M_MASK;
+    if constexpr (NHWC_OUT) {
+        // values to BF16 in this wavefront's 64 x 32 block of the (no longer needed)
+        // input tile, then each lane stores one pixel's 64 bytes with four 16-byte stores
+        static_assert(NB == 2, "pixel-major outputs carry all 32 channels");
+        __syncthreads();
+        __bf16* blk = &tile[0][0][0] + wv * STRIP * C;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        __syncthreads();
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[wv + dy][16 * m + r16 + dx][8 * kq]);
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb)
-                        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[dy * 3 + dx][nb], acc[m][nb], 0, 0, 0);
-                }
-        // epilogue: pixel x0 + 16 m + 4 kq + i, channel 16 nb + r16
-        constexpr bool NHWC_OUT = MODE == M_RELU || MODE == M_LOSS || MODE == M_MASK;
-        if constexpr (NHWC_OUT) {
-            // values to BF16 in this wavefront's 64 x 32 block of the (no longer needed)
-            // input tile, then each lane stores one pixel's 64 bytes with four 16-byte stores
-            static_assert(NB == 2, "pixel-major outputs carry all 32 channels");
-            __syncthreads();
-            __bf16* blk = &tile[0][0][0] + wv * STRIP * C;
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int lp = 16 * m + 4 * kq + i, xp = x0 + lp;
-                    const bool in = rowin && xp < W;
-                    const long long px = (long long)y * W + xp;
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        const int o = 16 * nb + r16;
-                        const float v = acc[m][nb][i];
-                        __bf16 r;
-                        if constexpr (MODE == M_RELU) {
-                            r = (__bf16)fmaxf(v + a.bias[o], 0.0f);
-                            if (in) pool[nb] += (float)r;
-                        } else if constexpr (MODE == M_LOSS) {
-                            float g = 0.0f;
-                            if (in && o < a.nout) {
-                                const float e = (v + a.bias[o]) - a.tgt[o * a.ps + px];
-                                g = e * a.gscale;
-                                lacc += (double)e * (double)e;
-                            }
-                            r = (__bf16)g;
-                        } else {
-                            const float sv = v + (a.addc ? a.addc[o] : 0.0f);
-                            r = (__bf16)((in && (float)a.mask[px * C + o] > 0.0f) ? sv : 0.0f);
-                        }
-                        blk[lp * C + o] = r;
-                    }
-                }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int xp = x0 + lane;
-            if (rowin && xp < W) {
+            for (int i = 0; i < 4; ++i) {
+                const int lp = 16 * m + 4 * kq + i, xp = x0 + lp;
+                const bool in = rowin && xp < W;
                 const long long px = (long long)y * W + xp;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    *reinterpret_cast<bf16x8*>(a.out_b + px * C + 8 * q) =
-                        *reinterpret_cast<const bf16x8*>(blk + lane * C + 8 * q);
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     const int o = 16 * nb + r16;
-                    const int xb = x0 + 16 * m + 4 * kq;
-                    if (!rowin) continue;
-                    const long long pb = (long long)y * W + xb;
-                    if constexpr (MODE == M_ADD) {
-                        if (o >= a.nout) continue;
-                        const float bo = a.bias[o];
-                        if ((W & 3) == 0 && xb + 3 < W) {
-                            const float4 up = *reinterpret_cast<const float4*>(a.uprev + o * a.ps + pb);
-                            float4 r;
-                            r.x = up.x + (acc[m][nb][0] + bo);
-                            r.y = up.y + (acc[m][nb][1] + bo);
-                            r.z = up.z + (acc[m][nb][2] + bo);
-                            r.w = up.w + (acc[m][nb][3] + bo);
-                            *reinterpret_cast<float4*>(a.out_f + o * a.ps + pb) = r;
-                        } else {
-#pragma unroll
-                            for (int i = 0; i < 4; ++i)
-                                if (xb + i < W) a.out_f[o * a.ps + pb + i] = a.uprev[o * a.ps + pb + i] + (acc[m][nb][i] + bo);
+                    const float v = acc[m][nb][i];
+                    __bf16 r;
+                    if constexpr (MODE == M_RELU) {
+                        r = (__bf16)fmaxf(v + a.bias[o], 0.0f);
+                        if (in) pool[nb] += (float)r;
+                    } else if constexpr (MODE == M_LOSS) {
+                        float g = 0.0f;
+                        if (in && o < a.nout) {
+                            const float e = (v + a.bias[o]) - a.tgt[o * a.ps + px];
+                            g = e * a.gscale;
+                            lacc += (double)e * (double)e;
                         }
+                        r = (__bf16)g;
+                    } else {
+                        const float sv = v + (a.addc ? a.addc[o] : 0.0f);
+                        r = (__bf16)((in && (float)a.mask[px * C + o] > 0.0f) ? sv : 0.0f);
+                    }
+                    blk[lp * C + o] = r;
+                }
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int xp = x0 + lane;
+        if (rowin && xp < W) {
+            const long long px = (long long)y * W + xp;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                *reinterpret_cast<bf16x8*>(a.out_b + px * C + 8 * q) =
+                    *reinterpret_cast<const bf16x8*>(blk + lane * C + 8 * q);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int o = 16 * nb + r16;
+                const int xb = x0 + 16 * m + 4 * kq;
+                if (!rowin) continue;
+                const long long pb = (long long)y * W + xb;
+                if constexpr (MODE == M_ADD) {
+                    if (o >= a.nout) continue;
+                    const float bo = a.bias[o];
+                    if ((W & 3) == 0 && xb + 3 < W) {
+                        const float4 up = *reinterpret_cast<const float4*>(a.uprev + o * a.ps + pb);
+                        float4 r;
+                        r.x = up.x + (acc[m][nb][0] + bo);
+                        r.y = up.y + (acc[m][nb][1] + bo);
+                        r.z = up.z + (acc[m][nb][2] + bo);
+                        r.w = up.w + (acc[m][nb][3] + bo);
+                        *reinterpret_cast<float4*>(a.out_f + o * a.ps + pb) = r;
                     } else {
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
-                            if (xb + i < W) a.out_f[(pb + i) * C + o] = acc[m][nb][i] + a.bias[o];
+                            if (xb + i < W) a.out_f[o * a.ps + pb + i] = a.uprev[o * a.ps + pb + i] + (acc[m][nb][i] + bo);
                     }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (xb + i < W) a.out_f[(pb + i) * C + o] = acc[m][nb][i] + a.bias[o];
                 }
             }
         }
@@ -440,9 +436,10 @@ __global__ void k_adam(float* p, float* m, float* v, const float* g, long long n
 
 // ------------------------------------------------------------ launchers
 
+// One workgroup per tile of 4 rows x 64 pixels (a persistent grid that loaded the weights once
+// per resident workgroup was measured slower).
 int conv_grid(int W, int H) {
-    const long long tiles = (long long)((W + STRIP - 1) / STRIP) * ((H + CONV_ROWS - 1) / CONV_ROWS);
-    return (int)(tiles < CONV_GRID_MAX ? tiles : CONV_GRID_MAX);
+    return ((W + STRIP - 1) / STRIP) * ((H + CONV_ROWS - 1) / CONV_ROWS);
 }
 
 hipError_t launch_conv(const ConvArgs& a, int nb, hipStream_t s) {

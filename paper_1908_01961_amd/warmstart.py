@@ -115,3 +115,44 @@ def transfer(net_from: Net, K: int, W: int, H: int) -> Net:
     net = Net(K, W, H)
     net.set_params(net_from.get_params())
     return net
+
+
+def bench_forward(K: int, W: int, H: int, reps: int = 20) -> float:
+    """Milliseconds per network forward pass at W x H (He-initialised weights with a
+    live output layer, random inputs on the device)."""
+    import torch
+    net = Net(K, W, H)
+    flat = init_params(K, 1)
+    flat[flat == 0] = 0.01
+    net.set_params(flat)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    fr = torch.rand((3, H, W), device="cuda", generator=g)
+    u = torch.rand((K + 4, H, W), device="cuda", generator=g)
+    uo = torch.empty_like(u)
+    for _ in range(3):
+        net.forward(fr, u, uo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.lib.gid_net_forward(net.h, net_ptr(fr), net_ptr(u), net_ptr(uo), None)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    net.close()
+    return ms
+
+
+def net_ptr(t):
+    from ctypes import c_void_p
+    return c_void_p(t.data_ptr())
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="time the warm-start network's forward pass")
+    ap.add_argument("--width", type=int, default=1280)
+    ap.add_argument("--height", type=int, default=720)
+    ap.add_argument("--K", type=int, default=8)
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args()
+    print(f"network forward {a.width}x{a.height} K={a.K}: {bench_forward(a.K, a.width, a.height, a.reps):.3f} ms",
+          flush=True)
