@@ -174,6 +174,79 @@ def learned_vs_plain(clip, w, train_frames: int, log):
                 speedup_at_matched_energy=round(best["learned"]["mpx_s"] / plain_mpx, 3) if best else None)
 
 
+def bench_batch(args, log):
+    """Sixteen clips of mixed size (320x240 ... 1280x720), length (8-32 frames) and K
+    (4-8), all advanced one frame per call through shared launches (gid_batch_*),
+    against the same contexts solving the clips one after another.  Each clip's
+    launch shape comes from the autotuner (untimed).  A step is one pass over
+    every frame of every clip, from the initial colours."""
+    import tempfile
+
+    import torch
+
+    import paper_1908_01961_amd as G
+    from scenes import make_clip, mixed_batch_specs
+
+    specs = mixed_batch_specs(16, 400)
+    clips = [make_clip(sp["width"], sp["height"], sp["K"], sp["frames"], sp["seed"]) for sp in specs]
+    log(f"{len(clips)} clips generated")
+    solvers = [G.Solver(c.width, c.height, G.default_params(c.K, gn_iters=3, pcg_iters=8, temporal=1,
+                                                            record_energy=0, use_graph=1)) for c in clips]
+    with tempfile.TemporaryDirectory() as d:
+        shapes = [s.autotune(f"{d}/tune.txt") for s in solvers]
+    frames = [torch.from_numpy(c.frames).cuda() for c in clips]
+    ids = [torch.from_numpy(c.ids).cuda() for c in clips]
+    Fmax = max(c.nframes for c in clips)
+    px = sum(c.nframes * c.width * c.height for c in clips)
+    batch = G.Batch(solvers)
+
+    def step_batch():
+        for s, c in zip(solvers, clips):
+            s.set_base_colors(c.b_init)
+        for t in range(Fmax):
+            batch.step_async([frames[i][t] if t < c.nframes else None for i, c in enumerate(clips)],
+                             [ids[i][t] if t < c.nframes else None for i, c in enumerate(clips)])
+            batch.synchronize()
+
+    def step_sequential():
+        for i, (s, c) in enumerate(zip(solvers, clips)):
+            s.set_base_colors(c.b_init)
+            for t in range(c.nframes):
+                s.decompose_frame_async(frames[i][t], ids[i][t])
+            s.synchronize()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    t_b = timed(step_batch)
+    log(f"batched: {t_b * 1e3:.1f} ms per pass, {px / t_b / 1e6:.1f} Mpx/s")
+    t_s = timed(step_sequential)
+    log(f"one clip after another: {t_s * 1e3:.1f} ms per pass, {px / t_s / 1e6:.1f} Mpx/s")
+    batch.close()
+    for s in solvers:
+        s.close()
+    out = {
+        "metric": "decomposed Mpixel/s at fixed final energy (1 GPU); learned warm-start vs plain",
+        "value": round(px / t_b / 1e6, 2), "unit": "Mpx/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(t_b * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (f64 reductions)", "data": "synthetic",
+        "config": {"workload": "batch_16_mixed", "clips": [dict(width=c.width, height=c.height, frames=c.nframes,
+                                                                K=c.K, workgroups=n) for c, n in zip(clips, shapes)],
+                   "pixels_per_step": px, "gn_iters": 3, "pcg_iters": 8, "temporal": True, "method": "plain"},
+        "sequential": {"mpx_s": round(px / t_s / 1e6, 2), "ms_per_step": round(t_s * 1e3, 3)},
+        "batched_over_sequential": round(t_s / t_b, 3),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +274,8 @@ def main() -> int:
     import paper_1908_01961_amd as G
     from scenes import WORKLOADS, workload_clip
 
+    if args.workload == "batch_16_mixed":
+        return bench_batch(args, lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     w = WORKLOADS[args.workload]
     F = args.frames or w["frames"]
     print(f"[bench] generating {args.workload} ({F} frames)", file=sys.stderr, flush=True)
