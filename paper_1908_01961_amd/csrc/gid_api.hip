@@ -973,8 +973,7 @@ struct gid_batch {
     std::vector<int> nb_snapshot;      // per-clip workgroup counts the batch was built with
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    int kb = 0;
-    void* dmem = nullptr;              // device: Args[n], wg_pix[n+1], wg_bs[n+1]
+    void* dmem = nullptr;              // device: Args[n], then per K group its wg_pix and wg_bs prefixes
     Args* d_args = nullptr;
     int* d_wg = nullptr;
     Args* h_args = nullptr;            // pinned staging of the same
@@ -1029,12 +1028,11 @@ gid_status gid_batch_create(gid_ctx* const* ctxs, int32_t n, gid_batch** out) {
     for (int i = 0; i < n; ++i) {
         b->clips.push_back(ctxs[i]);
         b->nb_snapshot.push_back(ctxs[i]->nblocks);
-        b->kb = std::max(b->kb, ctxs[i]->K);
     }
     const size_t args_bytes = align_up(sizeof(Args) * n, 256);
-    if (hipMalloc(&b->dmem, args_bytes + sizeof(int) * 2 * (n + 1)) != hipSuccess ||
+    if (hipMalloc(&b->dmem, args_bytes + sizeof(int) * 4 * (n + 1)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&b->h_args), sizeof(Args) * n) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&b->h_wg), sizeof(int) * 2 * (n + 1)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->h_wg), sizeof(int) * 4 * (n + 1)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(double) * 2 * n) != hipSuccess) {
         batch_release(b);
         delete b;
@@ -1079,42 +1077,63 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
     if (mode == GID_REFINE_FIRST_FRAME && first_count != 0 && first_count != (int)act.size())
         return bfail(b, GID_ERR_UNSUPPORTED, "refine-first-frame needs the active clips at the same frame");
     const bool refine = mode == GID_REFINE_EVERY_STEP || (mode == GID_REFINE_FIRST_FRAME && first_count > 0);
+    // active clips grouped by K (clips keep their relative order inside a group);
+    // every kernel of the step is launched once per group
+    std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return b->clips[x]->K < b->clips[y]->K; });
     const int na = (int)act.size();
-    int* wg_pix = b->h_wg;
-    int* wg_bs = b->h_wg + (na + 1);
-    wg_pix[0] = wg_bs[0] = 0;
-    for (int j = 0; j < na; ++j) {
-        gid_ctx* c = b->clips[act[j]];
-        Args a = base_args(c);
-        a.in_frame = frames[act[j]];
-        a.in_ids = ids[act[j]];
-        a.out = layers ? layers[act[j]] : nullptr;
-        a.first = c->frame_index == 0;
-        a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
-        b->h_args[j] = a;
-        wg_pix[j + 1] = wg_pix[j] + c->nblocks;
-        wg_bs[j + 1] = wg_bs[j] + c->nb_bs;
+    std::vector<BatchGrid> groups;
+    int* hw = b->h_wg;
+    int wofs = 0;
+    for (int j = 0; j < na;) {
+        const int K = b->clips[act[j]]->K;
+        int m = 0;
+        while (j + m < na && b->clips[act[j + m]]->K == K) ++m;
+        int* wg_pix = hw + wofs;
+        int* wg_bs = wg_pix + (m + 1);
+        wg_pix[0] = wg_bs[0] = 0;
+        for (int q = 0; q < m; ++q) {
+            gid_ctx* c = b->clips[act[j + q]];
+            Args a = base_args(c);
+            a.in_frame = frames[act[j + q]];
+            a.in_ids = ids[act[j + q]];
+            a.out = layers ? layers[act[j + q]] : nullptr;
+            a.first = c->frame_index == 0;
+            a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
+            b->h_args[j + q] = a;
+            wg_pix[q + 1] = wg_pix[q] + c->nblocks;
+            wg_bs[q + 1] = wg_bs[q] + c->nb_bs;
+        }
+        BatchGrid g;
+        g.args = b->d_args + j;
+        g.wg_pix = b->d_wg + wofs;
+        g.wg_bs = b->d_wg + wofs + (m + 1);
+        g.nclips = m;
+        g.total_pix = wg_pix[m];
+        g.total_bs = wg_bs[m];
+        g.k = K;
+        groups.push_back(g);
+        wofs += 2 * (m + 1);
+        j += m;
     }
     hipStream_t st = b->stream;
     GID_BHIP(b, hipMemcpyAsync(b->d_args, b->h_args, sizeof(Args) * na, hipMemcpyHostToDevice, st));
-    GID_BHIP(b, hipMemcpyAsync(b->d_wg, b->h_wg, sizeof(int) * 2 * (na + 1), hipMemcpyHostToDevice, st));
-    BatchGrid g;
-    g.args = b->d_args;
-    g.wg_pix = b->d_wg;
-    g.wg_bs = b->d_wg + (na + 1);
-    g.nclips = na;
-    g.total_pix = wg_pix[na];
-    g.total_bs = wg_bs[na];
-    g.kb = b->kb;
+    GID_BHIP(b, hipMemcpyAsync(b->d_wg, b->h_wg, sizeof(int) * wofs, hipMemcpyHostToDevice, st));
+    auto each = [&](Kern k, const Step& s, hipStream_t cs) {
+        for (const BatchGrid& g : groups) {
+            const hipError_t e = launch_batch(k, g, s, cs);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
     const Step s0{};
-    GID_BHIP(b, launch_batch(KN_RESET, g, s0, st));
-    GID_BHIP(b, launch_batch(KN_SCAN, g, s0, st));
-    GID_BHIP(b, launch_batch(KN_PRECOMPUTE, g, s0, st));
+    GID_BHIP(b, each(KN_RESET, s0, st));
+    GID_BHIP(b, each(KN_SCAN, s0, st));
+    GID_BHIP(b, each(KN_PRECOMPUTE, s0, st));
     const gid_params& prm = b->clips[0]->prm;
     auto enqueue = [&](hipStream_t cs) {
         int ns = 0;
         return enqueue_schedule(prm.gn_iters, prm.pcg_iters, refine, false,
-                                [&](Kern k, const Step& s) { return launch_batch(k, g, s, cs); }, &ns);
+                                [&](Kern k, const Step& s) { return each(k, s, cs); }, &ns);
     };
     if (prm.use_graph) {
         const auto key = std::make_pair(mask, refine ? 1 : 0);
@@ -1129,7 +1148,7 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
     } else {
         GID_BHIP(b, enqueue(st));
     }
-    GID_BHIP(b, launch_batch(KN_OUTPUT, g, s0, st));
+    GID_BHIP(b, each(KN_OUTPUT, s0, st));
     for (int j = 0; j < na; ++j) {
         gid_ctx* c = b->clips[act[j]];
         GID_BHIP(b, hipMemcpyAsync(b->h_out + 2 * act[j], c->elog + (long long)FINAL_SLOT * ELOG_STRIDE,

@@ -126,7 +126,7 @@ struct BatchGrid {
     const int* wg_bs;       // apply + base-colour-sum launches
     int nclips;
     int total_pix, total_bs;
-    int kb;                 // largest K in the batch (selects the compiled K bucket)
+    int k;                  // the K every clip of this launch has
 };
 
 // Launch one kernel for one clip / for a batch (returns the launch error).

@@ -14,10 +14,11 @@
 // contiguous chunk of tiles (one tile each while the frame has at most 2048
 // tiles), so a launch produces at most 2048 partial sums.
 // Every kernel is a body over (clip descriptor, launch context, step); a
-// single-clip launch runs it over its whole grid, a batched launch runs the
-// bodies of several clips of uneven size and K in one grid, each workgroup
-// finding its clip from a prefix table and branching to the body compiled for
-// that clip's K.
+// single-clip launch runs it over its whole grid, a batched launch runs it for
+// several clips of uneven size in one grid, each workgroup finding its clip
+// from a prefix table.  The clips of a batched launch share K (a batch with
+// several K issues one launch per K), so every kernel is compiled for exactly
+// its K and keeps that K's register allocation and occupancy.
 //
 // Precision: unknowns and PCG vectors are FP32; every dot product, alpha, beta,
 // base-colour sum, the 3K x 3K solve and the energy are FP64.  Reductions are
@@ -1169,19 +1170,6 @@ __device__ __forceinline__ Lc clip_grid(const int* wg, int c) {
     return Lc{xcd_order((int)blockIdx.x - wg[c], nb), nb};
 }
 
-// Run fn(std::integral_constant<int, K>) for the clip's K (1..KB).
-template <int KB, typename Fn>
-__device__ __forceinline__ void dispatch_K(int K, Fn&& fn) {
-    switch (K) {
-#define GID_CASE(V) \
-        case V: if constexpr (KB >= V) fn(std::integral_constant<int, V>{}); break;
-        GID_CASE(1) GID_CASE(2) GID_CASE(3) GID_CASE(4) GID_CASE(5) GID_CASE(6) GID_CASE(7) GID_CASE(8)
-        GID_CASE(9) GID_CASE(10) GID_CASE(11) GID_CASE(12) GID_CASE(13) GID_CASE(14) GID_CASE(15) GID_CASE(16)
-#undef GID_CASE
-        default: break;
-    }
-}
-
 #define GID_PIXEL_KERNELS(NAME, ATTR)                                                              \
     template <int K>                                                                               \
     __global__ __launch_bounds__(NTHREADS) ATTR(K) void k_##NAME(Args a, Step st) {                \
@@ -1189,13 +1177,13 @@ __device__ __forceinline__ void dispatch_K(int K, Fn&& fn) {
         NAME##_body<K>(a, whole_grid(), st, smem);                                                 \
     }                                                                                              \
     template <int KB>                                                                              \
-    __global__ __launch_bounds__(NTHREADS) ATTR(KB) void kb_##NAME(const Args* args, const int* wg, int nclips, \
-                                                               Step st) {                          \
+    __global__ __launch_bounds__(NTHREADS) ATTR(KB) void kb_##NAME(const Args* __restrict__ args, const int* wg,  \
+                                                                   int nclips, Step st) {          \
         extern __shared__ __align__(16) char smem[];                                               \
         const int c = clip_index(wg, nclips);                                                      \
         const Args& a = args[c];                                                                   \
         const Lc lc = clip_grid(wg, c);                                                            \
-        dispatch_K<KB>(a.K, [&](auto kc) { NAME##_body<decltype(kc)::value>(a, lc, st, smem); });  \
+        NAME##_body<KB>(a, lc, st, smem);                                                          \
     }
 
 // Occupancy targets.  The matvec's LDS tile limits a CU to lds_waves<K>()
@@ -1240,7 +1228,7 @@ template <int KB>
 __global__ __launch_bounds__(BSOLVE_THREADS) void kb_bsolve(const Args* args, Step st) {
     extern __shared__ __align__(16) char smem[];
     const Args& a = args[blockIdx.x];
-    dispatch_K<KB>(a.K, [&](auto kc) { bsolve_body<decltype(kc)::value>(a, Lc{0, 1}, st, smem); });
+    bsolve_body<KB>(a, Lc{0, 1}, st, smem);
 }
 __global__ __launch_bounds__(NTHREADS) void k_energy_finish(Args a, Step st) {
     extern __shared__ __align__(16) char smem[];
@@ -1274,13 +1262,6 @@ hipError_t with_K(int K, Fn&& fn) {
     return hipGetLastError();
 }
 
-template <typename Fn>
-hipError_t with_KB(int kb, Fn&& fn) {
-    if (kb <= 8) fn(std::integral_constant<int, 8>{});
-    else if (kb <= KMAX) fn(std::integral_constant<int, 16>{});
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-}
 }  // namespace
 
 hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
@@ -1340,7 +1321,7 @@ hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t 
         default:
             break;
     }
-    return with_KB(g.kb, [&](auto kc) {
+    return with_K(g.k, [&](auto kc) {
         constexpr int KB = decltype(kc)::value;
         switch (k) {
             case KN_PRECOMPUTE:
