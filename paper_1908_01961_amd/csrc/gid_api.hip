@@ -23,8 +23,7 @@ namespace {
 constexpr int FINAL_SLOT = ELOG_SLOTS - 2;   // energy of the frame when half-steps are not recorded
 constexpr int PROBE_SLOT = ELOG_SLOTS - 1;   // single-step energy evaluation
 constexpr int NB_MAX = 2048;                 // default cap on workgroups of a per-pixel launch (one tile each up to here)
-constexpr int NB_TUNE_MAX = 2048;            // largest workgroup count the autotuner may choose
-constexpr int NB_BS_MAX = 512;               // workgroups of the apply + base-colour-sum pass
+static_assert(NB_MAX <= NB_TUNE_MAX, "site totals unroll their loads up to NB_TUNE_MAX workgroups");
 constexpr uint32_t STATE_MAGIC = 0x67696431u; // "gid1"
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

@@ -21,6 +21,8 @@ constexpr int ELOG_STRIDE = 1 + NTERMS;   // total + terms per energy slot
 constexpr int ELOG_SLOTS = GID_MAX_HALF_STEPS + 4;
 constexpr int JUDGE_PREV_SLOT = ELOG_SLOTS - 4;    // warm-start judge: energy at the previous frame's result
 constexpr int JUDGE_NET_SLOT = ELOG_SLOTS - 3;     // warm-start judge: energy at the network's prediction
+constexpr int NB_TUNE_MAX = 2048;   // workgroups of a per-pixel launch (at most)
+constexpr int NB_BS_MAX = 512;   // workgroups of the apply + base-colour-sum pass (at most)
 
 // Slots of the device scalar array (doubles).
 enum Scal : int {

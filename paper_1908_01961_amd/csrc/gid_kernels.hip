@@ -77,10 +77,18 @@ __device__ __forceinline__ void publish(const Args& a, const Lc& lc, int site, c
 
 // Total of value v of a site produced by a launch of nb workgroups; every
 // thread gets the same result, summed in a fixed order.
+// The loads are unrolled up to the largest launch (nb <= NB_TUNE_MAX), so they
+// are all in flight together.
+constexpr int SITE_LOADS = NB_TUNE_MAX / NTHREADS;
+
 __device__ __forceinline__ double site_total(const Args& a, int site, int v, int nb, double* sh4) {
     const double* p = site_ptr(a, site) + (long long)v * nb;
     double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += NTHREADS) s += p[i];
+#pragma unroll
+    for (int j = 0; j < SITE_LOADS; ++j) {
+        const int i = (int)threadIdx.x + j * NTHREADS;
+        if (i < nb) s += p[i];
+    }
     return block_sum(s, sh4);
 }
 
@@ -863,17 +871,20 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
     if (a.scal[S_BADIN] != 0.0) return;
     const double* part = a.partials + (long long)R_BS * a.part_stride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    // eight sums per wavefront per round, so all their partial loads are in flight together
-    constexpr int U = 8;
+    // U sums per wavefront per round, every partial of a sum in one unrolled batch
+    // (nb <= NB_BS_MAX = 64 NCH), so each lane has U NCH independent loads in flight
+    constexpr int U = 4;
+    constexpr int NCH = NB_BS_MAX / 64;
     for (int e0 = wave; e0 < NS; e0 += nw * U) {
         double s[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) s[u] = 0.0;
-        for (int b = lane; b < nb; b += 64) {
+        for (int u = 0; u < U; ++u) {
+            s[u] = 0.0;
+            const int e = e0 + u * nw;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int e = e0 + u * nw;
-                if (e < NS) s[u] += part[(long long)e * nb + b];
+            for (int j = 0; j < NCH; ++j) {
+                const int b = lane + 64 * j;
+                if (e < NS && b < nb) s[u] += part[(long long)e * nb + b];
             }
         }
 #pragma unroll
@@ -1098,8 +1109,21 @@ __device__ __forceinline__ void energy_finish_body(const Args& a, const Lc& lc, 
     const int nb = a.nblocks;
     double* sh4 = reinterpret_cast<double*>(smem);
     if (a.scal[S_BADIN] != 0.0) return;
+    // every term's partial loads in one batch, then the block reductions
+    const double* p = site_ptr(a, R_EN);
     double tot[NTERMS];
-    for (int v = 0; v < NTERMS; ++v) tot[v] = site_total(a, R_EN, v, nb, sh4);
+#pragma unroll
+    for (int v = 0; v < NTERMS; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < SITE_LOADS; ++j) {
+            const int i = (int)threadIdx.x + j * NTHREADS;
+            if (i < nb) s += p[(long long)v * nb + i];
+        }
+        tot[v] = s;
+    }
+#pragma unroll
+    for (int v = 0; v < NTERMS; ++v) tot[v] = block_sum(tot[v], sh4);
     if (threadIdx.x == 0) {
         double* slot = a.elog + (long long)st.slot * ELOG_STRIDE;
         double s = 0.0;
