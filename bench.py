@@ -9,8 +9,9 @@ device memory before timing starts; per-frame layers are written to device
 memory.  Default workload: 640x480, 30 frames, K = 6, G x P = 3 x 8.
 
 Prints one JSON line.  Besides the throughput it reports the roofline of the
-dominant kernel (the matrix-free J^T J matvec, timed with HIP events on the
-solver's stream in a profiled pass over the same clip) and the FP64 oracle
+dominant kernel (the PCG iteration: vector updates fused with the matrix-free
+J^T J product, timed with HIP events on the solver's stream in a profiled pass
+over the same clip) and the FP64 oracle
 timed on host cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -30,10 +31,18 @@ HBM_PEAK_GBS = 8000.0
 
 def algorithmic_bytes(n: int, tau: int, G: int, P: int) -> dict:
     """Bytes per pixel the method must move with FP32 state and the operator
-    recomputed from the unknowns (q kept on chip in a fused PCG iteration)."""
-    return dict(pcg_iter=4 * (7 * n + 1 + tau),
-                matvec=4 * (3 * n + 1 + tau),     # read p, u, w_SR, pair count; write q
-                frame=4 * G * (P * (7 * n + 1 + tau) + 7 * n + 7 + 3 * tau))
+    recomputed from the unknowns.  A PCG iteration i > 0 reads u, r, q, p, x and
+    M^-1 (n planes each), the soft-Retinex weight and the temporal pair count,
+    and writes x, r, p and q; the first iteration reads u, r0, p0 and M^-1 and
+    writes q.  The build reads u, the frame, the weight and the temporal sums
+    and writes r0, M^-1, p0 and x; the apply reads u, x and p and writes u."""
+    it_first = 5 * n + 1 + tau
+    it_next = 10 * n + 1 + tau
+    pcg_total = it_first + (P - 1) * it_next if P > 0 else 0
+    build = 5 * n + 4 + 4 * tau
+    apply = 4 * n + 3
+    return dict(pcg=4 * pcg_total / max(P, 1),            # average per PCG launch
+                frame=4 * G * (pcg_total + build + apply))
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -323,16 +332,16 @@ def main() -> int:
     step()
     kt = solver.kernel_times()
     solver.set_profiling(False)
-    mv = kt["matvec"]
+    mv = kt["pcg"]
     mv_avg_s = mv["ms"] / max(1, mv["launches"]) / 1e3
     tau = 1 if w["temporal"] else 0
     ab = algorithmic_bytes(n, tau, w["G"], w["P"])
-    mv_bytes = ab["matvec"] * W_ * H_
+    mv_bytes = ab["pcg"] * W_ * H_
     achieved = mv_bytes / mv_avg_s / 1e9
     frame_ms = ms_per_step / F
     frame_gbs = ab["frame"] * W_ * H_ / (frame_ms / 1e3) / 1e9
-    roofline = dict(bound="hbm", kernel="k_matvec", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic("k_matvec", args.workload),
+    roofline = dict(bound="hbm", kernel="k_pcg", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic("k_pcg", args.workload),
                     algorithmic_bytes_per_launch=mv_bytes, avg_launch_us=round(mv_avg_s * 1e6, 2))
     kernels = {k: dict(avg_us=round(v["ms"] * 1e3 / v["launches"], 2), launches=v["launches"],
                        share=round(v["ms"] / max(1e-12, sum(x["ms"] for x in kt.values())), 4))

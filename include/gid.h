@@ -194,9 +194,9 @@ gid_status gid_base_step(gid_ctx *ctx, int32_t *accepted);
  * with a HIP event pair around every launch on the context's stream; the
  * elapsed times are accumulated per kernel kind at gid_synchronize. */
 enum {
-    GID_KERNEL_SCAN = 0, GID_KERNEL_PRECOMPUTE, GID_KERNEL_GN_BUILD, GID_KERNEL_MATVEC,
-    GID_KERNEL_UPDATE, GID_KERNEL_APPLY_BSUM, GID_KERNEL_BSOLVE, GID_KERNEL_ENERGY,
-    GID_KERNEL_OUTPUT, GID_NUM_KERNEL_KINDS
+    GID_KERNEL_SCAN = 0, GID_KERNEL_PRECOMPUTE, GID_KERNEL_GN_BUILD, GID_KERNEL_PCG,
+    GID_KERNEL_APPLY_BSUM, GID_KERNEL_BSOLVE, GID_KERNEL_ENERGY, GID_KERNEL_OUTPUT,
+    GID_NUM_KERNEL_KINDS
 };
 /* Turn profiling on (1) or off (0); turning it on clears the accumulated times. */
 gid_status gid_set_profiling(gid_ctx *ctx, int32_t enable);

@@ -38,7 +38,7 @@ struct gid_ctx {
     int device = 0;
     void* arena = nullptr;
     // device workspace
-    float *u = nullptr, *delta = nullptr, *res = nullptr, *pA = nullptr, *pB = nullptr, *q = nullptr,
+    float *u = nullptr, *delta = nullptr, *rA = nullptr, *rB = nullptr, *pA = nullptr, *pB = nullptr, *qA = nullptr, *qB = nullptr,
           *minv = nullptr, *I = nullptr, *wsr = nullptr, *tg = nullptr, *Iprev = nullptr,
           *rprev = nullptr, *bf = nullptr, *lnb = nullptr, *bcf = nullptr;
     uint8_t* ids = nullptr;
@@ -133,8 +133,7 @@ int kind_of(Kern k) {
         case KN_SCAN: return GID_KERNEL_SCAN;
         case KN_PRECOMPUTE: return GID_KERNEL_PRECOMPUTE;
         case KN_GN_BUILD: return GID_KERNEL_GN_BUILD;
-        case KN_MATVEC: return GID_KERNEL_MATVEC;
-        case KN_UPDATE: return GID_KERNEL_UPDATE;
+        case KN_PCG: return GID_KERNEL_PCG;
         case KN_APPLY_BSUM: return GID_KERNEL_APPLY_BSUM;
         case KN_BSOLVE: return GID_KERNEL_BSOLVE;
         case KN_ENERGY: return GID_KERNEL_ENERGY;
@@ -188,10 +187,12 @@ Args base_args(const gid_ctx* c) {
     a.cr_literal = c->prm.cr_mode == GID_CR_LITERAL;
     a.u = c->u;
     a.delta = c->delta;
-    a.res = c->res;
+    a.rA = c->rA;
+    a.rB = c->rB;
     a.pA = c->pA;
     a.pB = c->pB;
-    a.q = c->q;
+    a.qA = c->qA;
+    a.qB = c->qB;
     a.minv = c->minv;
     a.I = c->I;
     a.ids = c->ids;
@@ -291,8 +292,7 @@ hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& l
         if ((e = launch(KN_GN_BUILD, s)) != hipSuccess) return e;
         for (int i = 0; i < P; ++i) {
             s.iter = i;
-            if ((e = launch(KN_MATVEC, s)) != hipSuccess) return e;
-            if ((e = launch(KN_UPDATE, s)) != hipSuccess) return e;
+            if ((e = launch(KN_PCG, s)) != hipSuccess) return e;
         }
         s.refine = refine ? 1 : 0;
         s.add_delta = 1;
@@ -477,9 +477,9 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
         return o;
     };
     const size_t fplane = sizeof(float) * (size_t)c->ps;
-    const size_t o_u = take(fplane * c->n), o_delta = take(fplane * c->n), o_res = take(fplane * c->n),
-                 o_pA = take(fplane * c->n), o_pB = take(fplane * c->n), o_q = take(fplane * c->n),
-                 o_minv = take(fplane * c->n), o_I = take(fplane * 3), o_wsr = take(fplane),
+    const size_t o_u = take(fplane * c->n), o_delta = take(fplane * c->n), o_rA = take(fplane * c->n),
+                 o_rB = take(fplane * c->n), o_pA = take(fplane * c->n), o_pB = take(fplane * c->n),
+                 o_qA = take(fplane * c->n), o_qB = take(fplane * c->n), o_minv = take(fplane * c->n), o_I = take(fplane * 3), o_wsr = take(fplane),
                  o_tg = take(fplane * 4), o_Iprev = take(fplane * 3), o_rprev = take(fplane * 3);
     const size_t o_ids = take((size_t)c->ps);
     const size_t o_bf = take(sizeof(float) * 3 * KMAX);
@@ -501,10 +501,12 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     auto fp = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
     c->u = fp(o_u);
     c->delta = fp(o_delta);
-    c->res = fp(o_res);
+    c->rA = fp(o_rA);
+    c->rB = fp(o_rB);
     c->pA = fp(o_pA);
     c->pB = fp(o_pB);
-    c->q = fp(o_q);
+    c->qA = fp(o_qA);
+    c->qB = fp(o_qB);
     c->minv = fp(o_minv);
     c->I = fp(o_I);
     c->wsr = fp(o_wsr);
@@ -806,7 +808,7 @@ gid_status gid_apply_normal(gid_ctx* c, const float* p, float* q) {
     s.debug = 1;
     a.pdebug = p;
     a.out = q;
-    GID_HIP(c, launch_kernel(KN_MATVEC, a, s, c->stream));
+    GID_HIP(c, launch_kernel(KN_PCG, a, s, c->stream));
     GID_HIP(c, hipStreamSynchronize(c->stream));
     return GID_OK;
 }
@@ -818,8 +820,7 @@ gid_status gid_layer_step(gid_ctx* c, double* rz) {
     GID_HIP(c, launch_kernel(KN_GN_BUILD, a, s, c->stream));
     for (int i = 0; i < c->prm.pcg_iters; ++i) {
         s.iter = i;
-        GID_HIP(c, launch_kernel(KN_MATVEC, a, s, c->stream));
-        GID_HIP(c, launch_kernel(KN_UPDATE, a, s, c->stream));
+        GID_HIP(c, launch_kernel(KN_PCG, a, s, c->stream));
     }
     s.refine = 0;
     s.add_delta = 1;
@@ -1229,15 +1230,15 @@ gid_status gid_autotune(gid_ctx* c, const char* cache_path, int32_t* chosen) {
         Args a = step_args(c);
         Step s{};
         s.debug = 1;
-        a.out = c->q;
+        a.out = c->qA;
         a.out2 = c->minv;
         a.pdebug = c->pA;
         float ms_total = 0.0f;
         for (int rep = 0; rep < 4; ++rep) {
             if (hipEventRecord(e0, c->stream) != hipSuccess ||
                 launch_kernel(KN_GN_BUILD, a, s, c->stream) != hipSuccess ||
-                launch_kernel(KN_MATVEC, a, s, c->stream) != hipSuccess ||
-                launch_kernel(KN_MATVEC, a, s, c->stream) != hipSuccess ||
+                launch_kernel(KN_PCG, a, s, c->stream) != hipSuccess ||
+                launch_kernel(KN_PCG, a, s, c->stream) != hipSuccess ||
                 hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 status = fail(c, GID_ERR_HIP, "autotune launch failed");
                 break;

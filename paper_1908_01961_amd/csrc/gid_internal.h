@@ -38,8 +38,14 @@ enum Scal : int {
 };
 
 // Reduction buffers (one partial array and ticket per reduction site).
-// <r, z> alternates between R_RZA and R_RZB by PCG iteration parity.
-enum RedSite : int { R_RZA = 0, R_RZB, R_PQ, R_EN, R_BS, R_SCAN, NRED };
+// R_RZ0: <r0, z0> of the Gauss-Newton build; PCG iteration i publishes its sums
+// (PcgVal) to R_PCGA / R_PCGB by the parity of i.
+enum RedSite : int { R_RZ0 = 0, R_PCGA, R_PCGB, R_EN, R_BS, R_SCAN, NRED };
+
+// Per-workgroup sums of one PCG iteration: <p, q>, <q, z>, <q, M^-1 q>, <r, z>
+// with q = A p and z = M^-1 r.
+enum PcgVal : int { PV_PQ = 0, PV_QZ, PV_QMQ, PV_RZ, PV_N };
+static_assert(PV_N <= NTERMS, "a reduction site holds NTERMS values per workgroup");
 
 struct Lam {
     float data, cl, rs, p, rc, mo, is, sm, nn, ir, cr;
@@ -73,12 +79,14 @@ struct Args {
     int first;               // initialise the unknowns (first frame of a clip)
     int cr_literal;
     float* u;                // n planes
-    float* delta;
-    float* res;
+    float* delta;            // x: the layer step accumulated by PCG
+    float* rA;               // residual r, even PCG iterations (and r0)
+    float* rB;               // residual r, odd iterations
     float* pA;               // search direction, even iterations (and p0)
     float* pB;               // search direction, odd iterations
-    float* q;
-    float* minv;
+    float* qA;               // q = A p, even iterations
+    float* qB;               // q = A p, odd iterations
+    float* minv;             // Jacobi preconditioner M^-1 (inverse diagonal of A)
     float* I;                // 3 planes (frame copy)
     uint8_t* ids;
     float* wsr;              // 1 plane
@@ -116,7 +124,7 @@ struct Args {
 __host__ __device__ inline int bstep_nsums(int K) { return 3 * K * (K + 1) / 2 + 3 * K; }
 
 enum Kern : int {
-    KN_RESET = 0, KN_SCAN, KN_PRECOMPUTE, KN_GN_BUILD, KN_MATVEC, KN_UPDATE, KN_APPLY_BSUM, KN_BSOLVE,
+    KN_RESET = 0, KN_SCAN, KN_PRECOMPUTE, KN_GN_BUILD, KN_PCG, KN_APPLY_BSUM, KN_BSOLVE,
     KN_ENERGY, KN_ENERGY_FINISH, KN_OUTPUT, KN_TABLES, KN_CAND_TABLES, KN_JUDGE
 };
 

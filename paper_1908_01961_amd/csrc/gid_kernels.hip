@@ -1,5 +1,6 @@
 // HIP kernels of libgid for gfx950: the per-frame precompute, the layer step
-// (Gauss-Newton build, matrix-free J^T J matvec, PCG update), the apply +
+// (Gauss-Newton build, one launch per PCG iteration: vector updates and the
+// matrix-free J^T J product fused, one reduction per iteration), the apply +
 // base-colour sums, the small FP64 base-colour solve, the FP64 energy and the
 // output pass.
 //
@@ -77,24 +78,83 @@ __device__ __forceinline__ void publish(const Args& a, const Lc& lc, int site, c
 
 // Total of value v of a site produced by a launch of nb workgroups; every
 // thread gets the same result, summed in a fixed order.
-// The loads are unrolled up to the largest launch (nb <= NB_TUNE_MAX), so they
-// are all in flight together.
+// The loads are unrolled up to the largest launch (nb <= NB_TUNE_MAX) and issued
+// unconditionally (index clamped, value masked), so no branch separates them and
+// they are all in flight together.
 constexpr int SITE_LOADS = NB_TUNE_MAX / NTHREADS;
+
+__device__ __forceinline__ double masked_load(const double* p, int i, int n) {
+    const double x = p[i < n ? i : n - 1];
+    return i < n ? x : 0.0;
+}
 
 __device__ __forceinline__ double site_total(const Args& a, int site, int v, int nb, double* sh4) {
     const double* p = site_ptr(a, site) + (long long)v * nb;
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < SITE_LOADS; ++j) {
-        const int i = (int)threadIdx.x + j * NTHREADS;
-        if (i < nb) s += p[i];
-    }
+    for (int j = 0; j < SITE_LOADS; ++j) s += masked_load(p, (int)threadIdx.x + j * NTHREADS, nb);
     return block_sum(s, sh4);
 }
 
-// PCG inner-product sites: <r, z> after PCG iteration i lives in site rz_site(i);
-// iteration -1 is the Gauss-Newton build.
-__device__ __forceinline__ int rz_site(int i) { return (i & 1) ? R_RZB : R_RZA; }
+// Totals of the first NV values of a site, every partial load issued before the
+// first block reduction.
+template <int NV>
+__device__ __forceinline__ void site_totals(const Args& a, int site, int nb, double* sh4, double* out) {
+    const double* p = site_ptr(a, site);
+    double s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        s[v] = 0.0;
+#pragma unroll
+        for (int j = 0; j < SITE_LOADS; ++j) s[v] += masked_load(p + (long long)v * nb, (int)threadIdx.x + j * NTHREADS, nb);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) out[v] = block_sum(s[v], sh4);
+}
+
+// NV sums over the 256 threads with one pair of barriers (sh: 4 NV doubles);
+// every thread gets the results, combined in the order block_sum uses.
+template <int NV>
+__device__ __forceinline__ void block_sums(double* v, double* sh) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) sh[(threadIdx.x >> 6) * NV + j] = v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = (sh[j] + sh[NV + j]) + (sh[2 * NV + j] + sh[3 * NV + j]);
+}
+
+// PCG vectors of iteration i (ping-pong by parity; the build writes r0 and p0
+// into the even buffers).
+__device__ __forceinline__ int pcg_site(int i) { return (i & 1) ? R_PCGB : R_PCGA; }
+__device__ __forceinline__ float* p_buf(const Args& a, int i) { return (i & 1) ? a.pB : a.pA; }
+__device__ __forceinline__ float* r_buf(const Args& a, int i) { return (i & 1) ? a.rB : a.rA; }
+__device__ __forceinline__ float* q_buf(const Args& a, int i) { return (i & 1) ? a.qB : a.qA; }
+
+// The step length of PCG iteration i and the preconditioned residual norm that
+// follows it, from the sums the iteration published:
+//   alpha_i = <r_i, z_i> / <p_i, q_i>,
+//   <r_i+1, z_i+1> = <r_i, z_i> - 2 alpha_i <q_i, z_i> + alpha_i^2 <q_i, M^-1 q_i>
+// (r_i+1 = r_i - alpha_i q_i, z = M^-1 r), so the next iteration's beta needs no
+// reduction of its own.  ok is false on breakdown (<p, q> not positive or not finite).
+struct PcgScalars {
+    double rz, alpha, rz_next;
+    bool ok;
+};
+__device__ __forceinline__ PcgScalars pcg_scalars(const Args& a, int i, int nb, double* sh4) {
+    double t[PV_N];
+    site_totals<PV_N>(a, pcg_site(i), nb, sh4, t);
+    PcgScalars s;
+    s.rz = t[PV_RZ];
+    s.ok = t[PV_PQ] > 0.0 && isfinite(t[PV_PQ]);
+    s.alpha = s.ok ? s.rz / t[PV_PQ] : 0.0;
+    s.rz_next = s.rz - 2.0 * s.alpha * t[PV_QZ] + s.alpha * s.alpha * t[PV_QMQ];
+    return s;
+}
 
 // Visit every pixel of this workgroup's contiguous chunk of tiles: f(x, y, i).
 template <typename F>
@@ -156,21 +216,6 @@ __device__ __forceinline__ void load3(const float* base, long long ps, long long
     v[0] = base[i];
     v[1] = base[ps + i];
     v[2] = base[2 * ps + i];
-}
-
-// Search-direction buffers: iteration i writes p into p_new(i); its predecessor
-// is p_old(i) (the build writes p0 into pA).
-__device__ __forceinline__ float* p_new(const Args& a, int i) { return (i & 1) ? a.pB : a.pA; }
-__device__ __forceinline__ float* p_old(const Args& a, int i) { return (i == 0 || !((i - 1) & 1)) ? a.pA : a.pB; }
-
-// p of the current PCG iteration at plane element j: the stored p0 for the first
-// iteration, z + beta p_old afterwards in FP32 (a PCG vector operation; beta
-// itself is the FP64 ratio of two FP64 dot products, rounded once), recomputed
-// identically by every reader.
-__device__ __forceinline__ float p_at(const Args& a, const float* pold, bool first, long long j, float beta) {
-    if (first) return pold[j];
-    const float z = a.res[j] * a.minv[j];
-    return fmaf(beta, pold[j], z);
 }
 
 // --------------------------------------------------------------- input scan
@@ -276,7 +321,7 @@ __device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, con
 
 // ------------------------------------------------------- halo-staged tiles
 
-// The stencil kernels (GN build, matvec) stage a 66 x 6 halo'd tile of every
+// The stencil kernels (GN build, PCG iteration) stage a 66 x 6 halo'd tile of every
 // plane they read into LDS with one load phase, then read neighbours from LDS.
 constexpr int HW = TX + 2;          // halo'd tile width
 constexpr int HH = TYW + 2;         // halo'd tile height (tiles of 64 x 4 pixels)
@@ -438,7 +483,7 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
                 for (int v = 0; v < N; ++v) {
                     const float mi = 1.0f / M[v];
                     const float z = g[v] * mi;
-                    a.res[v * ps + i] = g[v];
+                    a.rA[v * ps + i] = g[v];
                     a.minv[v * ps + i] = mi;
                     a.pA[v * ps + i] = z;
                     a.delta[v * ps + i] = 0.0f;
@@ -450,64 +495,187 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
     }
     if (st.debug) return;
     const double vals[1] = {block_sum(acc, sh4)};
-    publish(a, lc, rz_site(-1), vals, 1);
+    publish(a, lc, R_RZ0, vals, 1);
     if (lead_thread(lc)) a.scal[S_STOP] = 0.0;
 }
 
-// ---------------------------------------------------------------- PCG matvec
+// ------------------------------------------------------------ PCG iteration
+
+// One Jacobi-PCG iteration i of the layer step per launch, the standard
+// recurrence rearranged so that it needs one grid-wide reduction per iteration:
+//   i > 0: alpha_{i-1}, beta_{i-1} from the sums of iteration i-1, then
+//          x += alpha p_{i-1},  r_i = r_{i-1} - alpha q_{i-1},  z_i = M^-1 r_i,
+//          p_i = z_i + beta p_{i-1};
+//   all:   q_i = A p_i (J^T W J applied matrix-free from the unknowns), and the
+//          sums <p_i, q_i>, <q_i, z_i>, <q_i, M^-1 q_i>, <r_i, z_i>.
+// The vector updates are FP32 (the two axpys through FP64, rounded once); p_i
+// is recomputed identically on the one-pixel halo of the tile, so the staged
+// search direction needs no separate pass.  The last iteration's x update is
+// applied by the apply pass.  Debug launches apply A to a caller vector.
+constexpr int NHALO = 2 * HW + 2 * TYW;   // halo elements of a 64 x 4 tile
+static_assert(NHALO <= NTHREADS, "one halo element per thread");
 
 template <int K>
-__device__ __forceinline__ void matvec_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
+__device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
-    double* sh4 = reinterpret_cast<double*>(smem);
-    float* Ul = reinterpret_cast<float*>(smem + 32);   // unknowns (r planes, then T planes)
-    float* Pl = Ul + N * HN;                           // search direction p of this iteration
-    if (!st.debug && (a.scal[S_STOP] != 0.0 || a.scal[S_BADIN] != 0.0)) return;   // uniform over the grid
-    double beta = 0.0;
-    if (!st.debug && st.iter > 0) {
-        // beta of the previous iteration from the last two <r, z> totals
-        const double rz_now = site_total(a, rz_site(st.iter - 1), 0, lc.nb, sh4);
-        const double rz_before = site_total(a, rz_site(st.iter - 2), 0, lc.nb, sh4);
-        if (lead_thread(lc)) a.scal[S_RZ_LOG + (st.gn & 63)] = rz_now;
-        if (rz_now == 0.0) {      // converged exactly: the rest of the layer step is a no-op
-            if (lead_thread(lc)) a.scal[S_STOP] = 1.0;
-            return;
-        }
-        beta = rz_now / rz_before;
-    }
-    // single-step access applies J^T J to a caller vector
-    const bool pfirst = st.debug || st.iter == 0;
-    const float betaf = (float)beta;
-    const float* pold = st.debug ? a.pdebug : p_old(a, st.iter);
-    float* pnw = p_new(a, st.iter);
+    double* shr = reinterpret_cast<double*>(smem);             // 4 PV_N doubles
+    float* Ul = reinterpret_cast<float*>(smem + 32 * PV_N);    // unknowns (r planes, then T planes)
+    float* Pl = Ul + N * HN;                                   // search direction p_i
+    // colour basis first: loaded before this kernel's first store, it stays in
+    // scalar registers
     Basis<K> bs;
     bs.load(a.bf, a.bcf);
+    const bool dbg = st.debug != 0;
+    if (!dbg && (a.scal[S_STOP] != 0.0 || a.scal[S_BADIN] != 0.0)) return;   // uniform over the grid
+    const int it = st.iter;
+    const bool first = dbg || it == 0;
+    double alpha = 0.0;
+    float betaf = 0.0f;
+    if (!first) {
+        const PcgScalars ps_ = pcg_scalars(a, it - 1, lc.nb, shr);
+        if (!ps_.ok) {     // breakdown guard: iteration it-1 is not applied, the layer step ends
+            if (lead_thread(lc)) {
+                a.scal[S_STOP] = 1.0;
+                a.scal[S_BREAKDOWNS] += 1.0;
+                a.scal[S_RZ_LOG + (st.gn & 63)] = ps_.rz;
+            }
+            return;
+        }
+        alpha = ps_.alpha;
+        if (lead_thread(lc)) a.scal[S_RZ_LOG + (st.gn & 63)] = ps_.rz_next;
+        // a residual norm that rounding drove to zero or below restarts the
+        // directions (p = z)
+        betaf = ps_.rz_next > 0.0 ? (float)(ps_.rz_next / ps_.rz) : 0.0f;
+    }
+    const float* pold = dbg ? a.pdebug : p_buf(a, first ? 0 : it - 1);
+    const float* rold = r_buf(a, first ? 0 : it - 1);
+    const float* qold = q_buf(a, it - 1);
+    float* pcur = p_buf(a, it);
+    float* rcur = r_buf(a, it);
+    float* qcur = dbg ? a.out : q_buf(a, it);
     const Lam L = a.lam;
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int li = (ly + 1) * HW + lx + 1;
     const int off[4] = {1, HW, -1, -HW};
+    // this thread's halo element: the rows above and below the tile, then the
+    // left and right columns
+    const int ht = (int)threadIdx.x;
+    const int hrow = ht < HW ? 0 : (ht < 2 * HW ? TYW + 1 : 1 + ((ht - 2 * HW) >> 1));
+    const int hcol = ht < 2 * HW ? ht % HW : (((ht - 2 * HW) & 1) ? HW - 1 : 0);
     int t0, t1;
     chunk_of(a, lc, t0, t1);
-    double acc = 0.0;
+    double acc[PV_N];
+#pragma unroll
+    for (int v = 0; v < PV_N; ++v) acc[v] = 0.0;
     for (int tile = t0; tile < t1; ++tile) {
         const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TYW;
-        for (int idx = threadIdx.x; idx < HN; idx += NTHREADS) {
-            const int gx = x0 + idx % HW - 1, gy = y0 + idx / HW - 1;
+        const int x = x0 + lx, y = y0 + ly;
+        const bool own_in = x < W && y < H;
+        const long long i = (long long)y * W + x;
+        // own pixel: unknowns, then the vector updates of this iteration.  Loads
+        // are unconditional (an off-frame pixel reads pixel 0 and is masked), and
+        // the mode test sits outside the plane loops, so every load of a loop is
+        // in flight before the first use.
+        const long long io = own_in ? i : 0;
+        {
+            float uv[N];
+#pragma unroll
+            for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + io];
+            __builtin_amdgcn_sched_barrier(0);   // every load issued before the first store
+#pragma unroll
+            for (int v = 0; v < N; ++v) Ul[v * HN + li] = own_in ? uv[v] : 0.0f;
+        }
+        if (dbg || first) {
+            float pv[N];
+#pragma unroll
+            for (int v = 0; v < N; ++v) pv[v] = pold[v * ps + io];
+            if (!dbg) {
+                float rv[N], mv[N];
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    rv[v] = rold[v * ps + io];
+                    mv[v] = a.minv[v * ps + io];
+                }
+#pragma unroll
+                for (int v = 0; v < N; ++v) acc[PV_RZ] += own_in ? (double)rv[v] * (double)(rv[v] * mv[v]) : 0.0;
+            }
+#pragma unroll
+            for (int v = 0; v < N; ++v) Pl[v * HN + li] = own_in ? pv[v] : 0.0f;
+        } else {
+            float po[N], rv[N], qv[N], mv[N], xv[N];
+#pragma unroll
+            for (int v = 0; v < N; ++v) {
+                const long long j = v * ps + io;
+                po[v] = pold[j];
+                rv[v] = rold[j];
+                qv[v] = qold[j];
+                mv[v] = a.minv[j];
+                xv[v] = a.delta[j];
+            }
+#pragma unroll
+            for (int v = 0; v < N; ++v) {
+                const float r = (float)((double)rv[v] - alpha * (double)qv[v]);
+                const float z = r * mv[v];
+                const float p = fmaf(betaf, po[v], z);
+                xv[v] = (float)((double)xv[v] + alpha * (double)po[v]);
+                rv[v] = r;
+                po[v] = p;
+                acc[PV_RZ] += own_in ? (double)r * (double)z : 0.0;
+                Pl[v * HN + li] = own_in ? p : 0.0f;
+            }
+            if (own_in) {
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    const long long j = v * ps + i;
+                    a.delta[j] = xv[v];
+                    rcur[j] = rv[v];
+                    pcur[j] = po[v];
+                }
+            }
+        }
+        // halo element: unknowns and p only (kept apart from the own pixel's
+        // loads, which the scheduler would otherwise interleave past the registers)
+        __builtin_amdgcn_sched_barrier(0);
+        if (ht < NHALO) {
+            const int gx = x0 + hcol - 1, gy = y0 + hrow - 1;
             const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-            const long long gi = (long long)gy * W + gx;
-            // all u loads, then all p loads, each fully unrolled so every load of
-            // the element is in flight before the first LDS store
+            const long long gi = in ? (long long)gy * W + gx : 0;
+            const int e = hrow * HW + hcol;
+            {
+                float uv[N];
 #pragma unroll
-            for (int v = 0; v < N; ++v) Ul[v * HN + idx] = in ? a.u[v * ps + gi] : 0.0f;
+                for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + gi];
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int v = 0; v < N; ++v) Pl[v * HN + idx] = in ? p_at(a, pold, pfirst, v * ps + gi, betaf) : 0.0f;
+                for (int v = 0; v < N; ++v) Ul[v * HN + e] = in ? uv[v] : 0.0f;
+            }
+            if (first) {
+                float pv[N];
+#pragma unroll
+                for (int v = 0; v < N; ++v) pv[v] = pold[v * ps + gi];
+#pragma unroll
+                for (int v = 0; v < N; ++v) Pl[v * HN + e] = in ? pv[v] : 0.0f;
+            } else {
+                float po[N], rv[N], qv[N], mv[N];
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    const long long j = v * ps + gi;
+                    po[v] = pold[j];
+                    rv[v] = rold[j];
+                    qv[v] = qold[j];
+                    mv[v] = a.minv[j];
+                }
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    const float r = (float)((double)rv[v] - alpha * (double)qv[v]);
+                    Pl[v * HN + e] = in ? fmaf(betaf, po[v], r * mv[v]) : 0.0f;
+                }
+            }
         }
         __syncthreads();
-        const int x = x0 + lx, y = y0 + ly;
-        if (x < W && y < H) {
-            const long long i = (long long)y * W + x;
+        if (own_in) {
             const bool hv[4] = {x + 1 < W, y + 1 < H, x > 0, y > 0};
             float p[N], q[N], T[K + 1], R[3], S[3];
 #pragma unroll
@@ -575,85 +743,27 @@ __device__ __forceinline__ void matvec_body(const Args& a, const Lc& lc, const S
                     q[3 + k] += ws * (p[3 + k] - Pl[(3 + k) * HN + li + off[d]]);
                 }
             }
-            if (st.debug) {
 #pragma unroll
-                for (int v = 0; v < N; ++v) a.out[v * ps + i] = q[v];
-            } else {
-#pragma unroll
-                for (int v = 0; v < N; ++v) {
-                    a.q[v * ps + i] = q[v];
-                    if (st.iter > 0) pnw[v * ps + i] = p[v];
-                    acc += (double)p[v] * (double)q[v];
+            for (int v = 0; v < N; ++v) {
+                qcur[v * ps + i] = q[v];
+                if (!dbg) {   // r_i and M^-1 read again (this thread wrote r_i) rather than held through the stencil
+                    const float mi = a.minv[v * ps + i];
+                    const float z = rcur[v * ps + i] * mi;
+                    acc[PV_PQ] += (double)p[v] * (double)q[v];
+                    acc[PV_QZ] += (double)q[v] * (double)z;
+                    acc[PV_QMQ] += (double)q[v] * (double)(q[v] * mi);
                 }
             }
         }
         __syncthreads();
     }
-    if (st.debug) return;
-    const double vals[1] = {block_sum(acc, sh4)};
-    publish(a, lc, R_PQ, vals, 1);
-}
-
-// ---------------------------------------------------------------- PCG update
-
-// Element-wise over the n contiguous planes of each vector, four elements per
-// thread per step: delta += alpha p, r -= alpha q, and the partial <r, M^-1 r>.
-template <int K>
-__device__ __forceinline__ void update_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
-    constexpr int N = K + 4;
-    double* sh4 = reinterpret_cast<double*>(smem);
-    if (a.scal[S_STOP] != 0.0 || a.scal[S_BADIN] != 0.0) return;
-    const double pq = site_total(a, R_PQ, 0, lc.nb, sh4);
-    const double rz = site_total(a, rz_site(st.iter - 1), 0, lc.nb, sh4);
-    if (!(pq > 0.0) || !isfinite(pq)) {       // breakdown guard: no update, layer step ends
-        if (lead_thread(lc)) {
-            a.scal[S_STOP] = 1.0;
-            a.scal[S_BREAKDOWNS] += 1.0;
-            a.scal[S_RZ_LOG + (st.gn & 63)] = rz;
-        }
-        return;
+    if (dbg) return;
+    block_sums<PV_N>(acc, shr);
+    if (threadIdx.x == 0) {
+        double* part = site_ptr(a, pcg_site(it));
+#pragma unroll
+        for (int v = 0; v < PV_N; ++v) part[(long long)v * lc.nb + lc.lb] = acc[v];
     }
-    const double alpha = rz / pq;
-    const long long total = (long long)N * a.ps;
-    const long long nvec = total / 4;
-    // contiguous element range of this workgroup (in float4 units), XCD-aware order
-    const int lb = lc.lb;
-    const long long v0 = (nvec * lb) / lc.nb, v1 = (nvec * (lb + 1)) / lc.nb;
-    double acc = 0.0;
-    float* pcur = p_new(a, st.iter);
-    const float4* P4 = reinterpret_cast<const float4*>(pcur);
-    const float4* Q4 = reinterpret_cast<const float4*>(a.q);
-    const float4* M4 = reinterpret_cast<const float4*>(a.minv);
-    float4* D4 = reinterpret_cast<float4*>(a.delta);
-    float4* R4 = reinterpret_cast<float4*>(a.res);
-    for (long long j = v0 + threadIdx.x; j < v1; j += NTHREADS) {
-        const float4 p = P4[j], q = Q4[j], mi = M4[j];
-        float4 d = D4[j], r = R4[j];
-        d.x = (float)((double)d.x + alpha * (double)p.x);
-        d.y = (float)((double)d.y + alpha * (double)p.y);
-        d.z = (float)((double)d.z + alpha * (double)p.z);
-        d.w = (float)((double)d.w + alpha * (double)p.w);
-        r.x = (float)((double)r.x - alpha * (double)q.x);
-        r.y = (float)((double)r.y - alpha * (double)q.y);
-        r.z = (float)((double)r.z - alpha * (double)q.z);
-        r.w = (float)((double)r.w - alpha * (double)q.w);
-        D4[j] = d;
-        R4[j] = r;
-        acc += (double)r.x * (double)(r.x * mi.x) + (double)r.y * (double)(r.y * mi.y) +
-               (double)r.z * (double)(r.z * mi.z) + (double)r.w * (double)(r.w * mi.w);
-    }
-    // tail elements (total not a multiple of 4), handled by the last workgroup
-    if (lb == lc.nb - 1) {
-        for (long long e = nvec * 4 + threadIdx.x; e < total; e += NTHREADS) {
-            const float dn = (float)((double)a.delta[e] + alpha * (double)pcur[e]);
-            const float rn = (float)((double)a.res[e] - alpha * (double)a.q[e]);
-            a.delta[e] = dn;
-            a.res[e] = rn;
-            acc += (double)rn * (double)(rn * a.minv[e]);
-        }
-    }
-    const double vals[1] = {block_sum(acc, sh4)};
-    publish(a, lc, rz_site(st.iter), vals, 1);
 }
 
 // ---------------------------------------------------- apply + base-colour sums
@@ -674,11 +784,28 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
     float (*Ts)[BS_STRIDE] = reinterpret_cast<float (*)[BS_STRIDE]>(smem + 32 + 6 * BS_STRIDE * 8 +
                                                                       NG * 3 * K * (K + 1) * 8);
     if (a.scal[S_BADIN] != 0.0) return;
-    if (st.log_rz && a.scal[S_STOP] == 0.0) {
-        // <r, z> after the last PCG iteration (site of iteration pcg_iters - 1)
-        const double rz = site_total(a, rz_site(st.iter), 0, a.nblocks, sh4);
-        if (lead_thread(lc)) a.scal[S_RZ_LOG + (st.gn & 63)] = rz;
+    // x += alpha p of the last PCG iteration (st.iter), applied with the layer step
+    // u += x; without PCG iterations x is zero and <r0, z0> is logged
+    double alpha = 0.0;
+    bool pend = false;
+    if (st.add_delta && a.scal[S_STOP] == 0.0) {
+        if (st.iter >= 0) {
+            const PcgScalars ps_ = pcg_scalars(a, st.iter, a.nblocks, sh4);
+            pend = ps_.ok;
+            alpha = ps_.alpha;
+            if (lead_thread(lc)) {
+                if (!ps_.ok) {   // breakdown guard: the iteration is not applied
+                    a.scal[S_STOP] = 1.0;
+                    a.scal[S_BREAKDOWNS] += 1.0;
+                }
+                if (st.log_rz) a.scal[S_RZ_LOG + (st.gn & 63)] = ps_.ok ? ps_.rz_next : ps_.rz;
+            }
+        } else if (st.log_rz) {
+            const double rz = site_total(a, R_RZ0, 0, a.nblocks, sh4);
+            if (lead_thread(lc)) a.scal[S_RZ_LOG + (st.gn & 63)] = rz;
+        }
     }
+    const float* plast = p_buf(a, st.iter < 0 ? 0 : st.iter);
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
     // this workgroup's contiguous chunk of tiles (XCD-aware)
@@ -712,7 +839,8 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
                 for (int v = 0; v < N; ++v) {
                     const long long e = v * ps + i;
                     if (st.add_delta) {
-                        uv[v] = a.u[e] + a.delta[e];
+                        const float x = pend ? (float)((double)a.delta[e] + alpha * (double)plast[e]) : a.delta[e];
+                        uv[v] = a.u[e] + x;
                         a.u[e] = uv[v];
                     } else {
                         uv[v] = a.u[e];
@@ -873,7 +1001,7 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     // U sums per wavefront per round, every partial of a sum in one unrolled batch
     // (nb <= NB_BS_MAX = 64 NCH), so each lane has U NCH independent loads in flight
-    constexpr int U = 4;
+    constexpr int U = K <= 9 ? 4 : 2;
     constexpr int NCH = NB_BS_MAX / 64;
     for (int e0 = wave; e0 < NS; e0 += nw * U) {
         double s[U];
@@ -881,11 +1009,9 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
         for (int u = 0; u < U; ++u) {
             s[u] = 0.0;
             const int e = e0 + u * nw;
+            const double* row = part + (long long)(e < NS ? e : NS - 1) * nb;
 #pragma unroll
-            for (int j = 0; j < NCH; ++j) {
-                const int b = lane + 64 * j;
-                if (e < NS && b < nb) s[u] += part[(long long)e * nb + b];
-            }
+            for (int j = 0; j < NCH; ++j) s[u] += masked_load(row, lane + 64 * j, nb);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1109,21 +1235,8 @@ __device__ __forceinline__ void energy_finish_body(const Args& a, const Lc& lc, 
     const int nb = a.nblocks;
     double* sh4 = reinterpret_cast<double*>(smem);
     if (a.scal[S_BADIN] != 0.0) return;
-    // every term's partial loads in one batch, then the block reductions
-    const double* p = site_ptr(a, R_EN);
     double tot[NTERMS];
-#pragma unroll
-    for (int v = 0; v < NTERMS; ++v) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < SITE_LOADS; ++j) {
-            const int i = (int)threadIdx.x + j * NTHREADS;
-            if (i < nb) s += p[(long long)v * nb + i];
-        }
-        tot[v] = s;
-    }
-#pragma unroll
-    for (int v = 0; v < NTERMS; ++v) tot[v] = block_sum(tot[v], sh4);
+    site_totals<NTERMS>(a, R_EN, nb, sh4, tot);
     if (threadIdx.x == 0) {
         double* slot = a.elog + (long long)st.slot * ELOG_STRIDE;
         double s = 0.0;
@@ -1171,7 +1284,7 @@ __device__ __forceinline__ void reset_frame_body(const Args& a, const Lc& lc, co
 
 constexpr size_t LDS_SMALL = 32;
 template <int K> constexpr size_t lds_gn_build() { return 32 + sizeof(float) * (K + 4) * HN; }
-template <int K> constexpr size_t lds_matvec() { return 32 + sizeof(float) * 2 * (K + 4) * HN; }
+template <int K> constexpr size_t lds_pcg() { return 32 * PV_N + sizeof(float) * 2 * (K + 4) * HN; }
 template <int K> constexpr size_t lds_apply_bsum() {
     return 32 + 6 * BS_STRIDE * 8 + (NTHREADS / ((3 * K <= 32) ? 32 : 64)) * 3 * K * (K + 1) * 8 +
            sizeof(float) * K * BS_STRIDE;
@@ -1210,24 +1323,22 @@ __device__ __forceinline__ Lc clip_grid(const int* wg, int c) {
         NAME##_body<KB>(a, lc, st, smem);                                                          \
     }
 
-// Occupancy targets.  The matvec's LDS tile limits a CU to lds_waves<K>()
-// workgroups (one wavefront of each per SIMD).  For K <= 6 the unconstrained
-// register allocation lands a few registers above that occupancy (K = 6: 100
-// VGPRs, four waves per SIMD instead of the five the LDS allows), so the
-// allocator is held to it; for larger K the natural allocation already fits.
+// Occupancy targets.  The PCG iteration's LDS tile limits a CU to lds_waves<K>()
+// workgroups (one wavefront of each per SIMD).  For K <= 6 the allocator is held
+// to that occupancy, at most six waves per SIMD (below 80 registers the small-K
+// kernels spill); for larger K the natural allocation is kept.
 template <int K> constexpr int lds_waves() {
-    constexpr int w = (int)((160 * 1024) / lds_matvec<K>());
+    constexpr int w = (int)((160 * 1024) / lds_pcg<K>());
     return w > 8 ? 8 : (w < 1 ? 1 : w);
 }
-template <int K> constexpr int mv_waves() { return K <= 6 ? lds_waves<K>() : 1; }
+template <int K> constexpr int mv_waves() { return K <= 6 ? (lds_waves<K>() < 6 ? lds_waves<K>() : 6) : 1; }
 #define GID_NO_ATTR(T)
 #define GID_GN_ATTR(T) __attribute__((amdgpu_waves_per_eu(4)))
 #define GID_MV_ATTR(T) __attribute__((amdgpu_waves_per_eu(mv_waves<T>())))
 
 GID_PIXEL_KERNELS(precompute, GID_NO_ATTR)
 GID_PIXEL_KERNELS(gn_build, GID_GN_ATTR)
-GID_PIXEL_KERNELS(matvec, GID_MV_ATTR)
-GID_PIXEL_KERNELS(update, GID_NO_ATTR)
+GID_PIXEL_KERNELS(pcg, GID_MV_ATTR)
 GID_PIXEL_KERNELS(apply_bsum, GID_NO_ATTR)
 GID_PIXEL_KERNELS(energy, GID_NO_ATTR)
 GID_PIXEL_KERNELS(output, GID_NO_ATTR)
@@ -1317,8 +1428,7 @@ hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
         switch (k) {
             case KN_PRECOMPUTE: hipLaunchKernelGGL(k_precompute<KK>, grid, blk, LDS_SMALL, s, a, st); break;
             case KN_GN_BUILD: hipLaunchKernelGGL(k_gn_build<KK>, grid, blk, lds_gn_build<KK>(), s, a, st); break;
-            case KN_MATVEC: hipLaunchKernelGGL(k_matvec<KK>, grid, blk, lds_matvec<KK>(), s, a, st); break;
-            case KN_UPDATE: hipLaunchKernelGGL(k_update<KK>, grid, blk, LDS_SMALL, s, a, st); break;
+            case KN_PCG: hipLaunchKernelGGL(k_pcg<KK>, grid, blk, lds_pcg<KK>(), s, a, st); break;
             case KN_APPLY_BSUM:
                 hipLaunchKernelGGL(k_apply_bsum<KK>, dim3(a.nb_bs), blk, lds_apply_bsum<KK>(), s, a, st);
                 break;
@@ -1354,11 +1464,8 @@ hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t 
             case KN_GN_BUILD:
                 hipLaunchKernelGGL(kb_gn_build<KB>, gpix, blk, lds_gn_build<KB>(), s, g.args, g.wg_pix, g.nclips, st);
                 break;
-            case KN_MATVEC:
-                hipLaunchKernelGGL(kb_matvec<KB>, gpix, blk, lds_matvec<KB>(), s, g.args, g.wg_pix, g.nclips, st);
-                break;
-            case KN_UPDATE:
-                hipLaunchKernelGGL(kb_update<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+            case KN_PCG:
+                hipLaunchKernelGGL(kb_pcg<KB>, gpix, blk, lds_pcg<KB>(), s, g.args, g.wg_pix, g.nclips, st);
                 break;
             case KN_APPLY_BSUM:
                 hipLaunchKernelGGL(kb_apply_bsum<KB>, gbs, blk, lds_apply_bsum<KB>(), s, g.args, g.wg_bs, g.nclips, st);

@@ -20,7 +20,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime er
           4: "non-finite value", 5: "call out of order", 6: "unsupported"}
 REFINE = {"off": 0, "first": 1, "every": 2}
 CR = {"chroma": 0, "literal": 1}
-KERNEL_KINDS = ("scan", "precompute", "gn_build", "matvec", "update", "apply_bsum", "bsolve", "energy",
+KERNEL_KINDS = ("scan", "precompute", "gn_build", "pcg", "apply_bsum", "bsolve", "energy",
                 "output")
 TERMS = ("data", "cluster", "rsparsity", "rconsist", "mono", "isparsity", "smooth", "nonneg")
 MAX_HALF = 128
