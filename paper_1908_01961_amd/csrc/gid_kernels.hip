@@ -238,8 +238,10 @@ __device__ __forceinline__ void scan_body(const Args& a, const Lc& lc, const Ste
 
 // ----------------------------------------------------------------- precompute
 
-__device__ __forceinline__ void chroma64(const float* I, long long ps, long long i, double floor_, double* C) {
-    const double v0 = I[i], v1 = I[ps + i], v2 = I[2 * ps + i];
+// Chromaticity of a pixel in FP64: its colour over its channel mean, or
+// (1, 1, 1) where the mean is below the floor.
+__device__ __forceinline__ void chroma64v(float f0, float f1, float f2, double floor_, double* C) {
+    const double v0 = f0, v1 = f1, v2 = f2;
     const double m = (v0 + v1 + v2) / 3.0;
     if (m >= floor_) {
         C[0] = v0 / m;
@@ -247,6 +249,29 @@ __device__ __forceinline__ void chroma64(const float* I, long long ps, long long
         C[2] = v2 / m;
     } else {
         C[0] = C[1] = C[2] = 1.0;
+    }
+}
+
+// The 3 x 3 window of the previous frame around (x, y) in row-major order: the
+// previous frame's colours and final r at each in-frame position (ok[w]).
+// Loads are unconditional (off-frame positions read the centre pixel) so all
+// of them are in flight together.
+struct Window3 {
+    float I[9][3], r[9][3];
+    bool ok[9];
+};
+__device__ __forceinline__ void load_window3(const Args& a, int x, int y, long long i, Window3& w) {
+    const long long ps = a.ps;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
+        w.ok[k] = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+        const long long jj = w.ok[k] ? (long long)yy * a.W + xx : i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            w.I[k][c] = a.Iprev[c * ps + jj];
+            w.r[k][c] = a.rprev[c * ps + jj];
+        }
     }
 }
 
@@ -275,29 +300,33 @@ __device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, con
         const uint8_t id = a.in_ids[i];
         a.ids[i] = id;
         double C[3], Cn[3];
-        chroma64(F, ps, i, floor_, C);
+        chroma64v(Iv[0], Iv[1], Iv[2], floor_, C);
+        // the four neighbours (right, left, down, up), loaded unconditionally
+        const bool hn[4] = {x + 1 < W, x > 0, y + 1 < H, y > 0};
+        const long long jn[4] = {hn[0] ? i + 1 : i, hn[1] ? i - 1 : i, hn[2] ? i + W : i, hn[3] ? i - W : i};
+        float Fn[4][3];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) load3(F, ps, jn[d], Fn[d]);
         double dC = 0.0;
-        if (x + 1 < W) { chroma64(F, ps, i + 1, floor_, Cn); dC = fmax(dC, cdist(Cn, C)); }
-        if (x > 0)     { chroma64(F, ps, i - 1, floor_, Cn); dC = fmax(dC, cdist(C, Cn)); }
-        if (y + 1 < H) { chroma64(F, ps, i + W, floor_, Cn); dC = fmax(dC, cdist(Cn, C)); }
-        if (y > 0)     { chroma64(F, ps, i - W, floor_, Cn); dC = fmax(dC, cdist(C, Cn)); }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            if (!hn[d]) continue;
+            chroma64v(Fn[d][0], Fn[d][1], Fn[d][2], floor_, Cn);
+            dC = fmax(dC, (d & 1) ? cdist(C, Cn) : cdist(Cn, C));
+        }
         a.wsr[i] = (float)(1.0 - exp(-(double)a.lam.rk * dC));
         float gsum = 0.0f, tr0 = 0.0f, tr1 = 0.0f, tr2 = 0.0f;
         if (a.temporal) {
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int yy = y + dy;
-                if (yy < 0 || yy >= H) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int xx = x + dx;
-                    if (xx < 0 || xx >= W) continue;
-                    const long long jj = (long long)yy * W + xx;
-                    chroma64(a.Iprev, ps, jj, floor_, Cn);
-                    if (cdist(C, Cn) < a.lam.gate) {
-                        gsum += 1.0f;
-                        tr0 += a.rprev[jj];
-                        tr1 += a.rprev[ps + jj];
-                        tr2 += a.rprev[2 * ps + jj];
-                    }
+            Window3 w;
+            load_window3(a, x, y, i, w);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                chroma64v(w.I[k][0], w.I[k][1], w.I[k][2], floor_, Cn);
+                if (w.ok[k] && cdist(C, Cn) < a.lam.gate) {
+                    gsum += 1.0f;
+                    tr0 += w.r[k][0];
+                    tr1 += w.r[k][1];
+                    tr2 += w.r[k][2];
                 }
             }
         }
@@ -392,9 +421,12 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
         for (int idx = threadIdx.x; idx < HN; idx += NTHREADS) {
             const int gx = x0 + idx % HW - 1, gy = y0 + idx / HW - 1;
             const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-            const long long gi = (long long)gy * W + gx;
-#pragma unroll 4
-            for (int v = 0; v < N; ++v) Ul[v * HN + idx] = in ? a.u[v * ps + gi] : 0.0f;
+            const long long gi = in ? (long long)gy * W + gx : 0;   // off-frame: read pixel 0, masked
+            float uv[N];
+#pragma unroll
+            for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + gi];
+#pragma unroll
+            for (int v = 0; v < N; ++v) Ul[v * HN + idx] = in ? uv[v] : 0.0f;
         }
         __syncthreads();
         const int x = x0 + lx, y = y0 + ly;
@@ -743,15 +775,26 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
                     q[3 + k] += ws * (p[3 + k] - Pl[(3 + k) * HN + li + off[d]]);
                 }
             }
+            if (dbg) {
 #pragma unroll
-            for (int v = 0; v < N; ++v) {
-                qcur[v * ps + i] = q[v];
-                if (!dbg) {   // r_i and M^-1 read again (this thread wrote r_i) rather than held through the stencil
-                    const float mi = a.minv[v * ps + i];
-                    const float z = rcur[v * ps + i] * mi;
+                for (int v = 0; v < N; ++v) qcur[v * ps + i] = q[v];
+            } else {
+                // r_i and M^-1 read again (this thread wrote r_i) rather than held
+                // through the stencil; all loads ahead of the q stores, which the
+                // compiler may not move them past
+                float rv[N], mv[N];
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    rv[v] = rcur[v * ps + i];
+                    mv[v] = a.minv[v * ps + i];
+                }
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    qcur[v * ps + i] = q[v];
+                    const float z = rv[v] * mv[v];
                     acc[PV_PQ] += (double)p[v] * (double)q[v];
                     acc[PV_QZ] += (double)q[v] * (double)z;
-                    acc[PV_QMQ] += (double)q[v] * (double)(q[v] * mi);
+                    acc[PV_QMQ] += (double)q[v] * (double)(q[v] * mv[v]);
                 }
             }
         }
@@ -834,16 +877,24 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
             const int sp = threadIdx.x;
             if (x < W && y < H) {
                 const long long i = (long long)y * W + x;
-                float uv[N];
+                float uv[N], Iv[3];
 #pragma unroll
-                for (int v = 0; v < N; ++v) {
-                    const long long e = v * ps + i;
-                    if (st.add_delta) {
-                        const float x = pend ? (float)((double)a.delta[e] + alpha * (double)plast[e]) : a.delta[e];
-                        uv[v] = a.u[e] + x;
-                        a.u[e] = uv[v];
-                    } else {
-                        uv[v] = a.u[e];
+                for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + i];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Iv[c] = a.I[c * ps + i];
+                if (st.add_delta) {
+                    // every load ahead of the u stores, which the compiler may not move them past
+                    float xv[N], pv[N];
+#pragma unroll
+                    for (int v = 0; v < N; ++v) {
+                        xv[v] = a.delta[v * ps + i];
+                        pv[v] = plast[v * ps + i];
+                    }
+#pragma unroll
+                    for (int v = 0; v < N; ++v) {
+                        const float x = pend ? (float)((double)xv[v] + alpha * (double)pv[v]) : xv[v];
+                        uv[v] = uv[v] + x;
+                        a.u[v * ps + i] = uv[v];
                     }
                 }
                 if (st.refine) {
@@ -854,7 +905,7 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
 #pragma unroll
                         for (int k = 0; k < K; ++k) S += B64[k][c] * (double)uv[4 + k];
                         Rs[c][sp] = R;
-                        Es[c][sp] = (double)a.I[c * ps + i] - R * S;
+                        Es[c][sp] = (double)Iv[c] - R * S;
                     }
 #pragma unroll
                     for (int k = 0; k < K; ++k) Ts[k][sp] = uv[4 + k];
@@ -1156,11 +1207,24 @@ __device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const S
 #pragma unroll
         for (int c = 0; c < 3; ++c) Bk[k][c] = a.b64[3 * k + c];
     for_each_pixel(a, lc, [&](int x, int y, long long i) {
+        constexpr int N = K + 4;
+        // the pixel and its right and lower neighbours (loaded unconditionally,
+        // the centre standing in for a missing neighbour)
+        const bool hr = x + 1 < W, hd = y + 1 < H;
+        const long long ir = hr ? i + 1 : i, id_ = hd ? i + W : i;
+        float uc[N], ur[N], ud[N], Ic[3];
+#pragma unroll
+        for (int v = 0; v < N; ++v) {
+            uc[v] = a.u[v * ps + i];
+            ur[v] = a.u[v * ps + ir];
+            ud[v] = a.u[v * ps + id_];
+        }
+        load3(a.I, ps, i, Ic);
         double r[3], T[K + 1];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) r[c] = a.u[c * ps + i];
+        for (int c = 0; c < 3; ++c) r[c] = uc[c];
 #pragma unroll
-        for (int k = 0; k <= K; ++k) T[k] = a.u[(3 + k) * ps + i];
+        for (int k = 0; k <= K; ++k) T[k] = uc[3 + k];
         const int id = a.ids[i];
         double S[3];
 #pragma unroll
@@ -1169,41 +1233,36 @@ __device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const S
 #pragma unroll
             for (int k = 0; k < K; ++k) s += Bk[k][c] * T[k + 1];
             S[c] = s;
-            const double d = (double)a.I[c * ps + i] - exp(r[c]) * s;
+            const double d = (double)Ic[c] - exp(r[c]) * s;
             e[0] += d * d;
             const double dc = r[c] - a.lnb64[3 * id + c];
             e[1] += dc * dc;
         }
         // reflectance-gradient norm (forward differences)
         double g2 = 0.0;
-        const bool hr = x + 1 < W, hd = y + 1 < H;
         if (hr) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { const double d = (double)a.u[c * ps + i + 1] - r[c]; g2 += d * d; }
+            for (int c = 0; c < 3; ++c) { const double d = (double)ur[c] - r[c]; g2 += d * d; }
         }
         if (hd) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { const double d = (double)a.u[c * ps + i + W] - r[c]; g2 += d * d; }
+            for (int c = 0; c < 3; ++c) { const double d = (double)ud[c] - r[c]; g2 += d * d; }
         }
         const double gn = sqrt(g2);
         e[2] += (p == 1.0) ? gn : ((gn > 0.0) ? pow(gn, p) : 0.0);
         if (a.temporal) {
             double C[3], Cn[3];
-            chroma64(a.I, ps, i, fl, C);
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int yy = y + dy;
-                if (yy < 0 || yy >= H) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int xx = x + dx;
-                    if (xx < 0 || xx >= W) continue;
-                    const long long jj = (long long)yy * W + xx;
-                    chroma64(a.Iprev, ps, jj, fl, Cn);
-                    if (cdist(C, Cn) < a.lam.gate) {
+            chroma64v(Ic[0], Ic[1], Ic[2], fl, C);
+            Window3 w;
+            load_window3(a, x, y, i, w);
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const double d = r[c] - (double)a.rprev[c * ps + jj];
-                            e[3] += d * d;
-                        }
+            for (int k = 0; k < 9; ++k) {
+                chroma64v(w.I[k][0], w.I[k][1], w.I[k][2], fl, Cn);
+                if (w.ok[k] && cdist(C, Cn) < a.lam.gate) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double d = r[c] - (double)w.r[k][c];
+                        e[3] += d * d;
                     }
                 }
             }
@@ -1216,8 +1275,8 @@ __device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const S
 #pragma unroll
         for (int k = 0; k <= K; ++k) {
             if (k > 0) e[5] += fabs(T[k]);
-            if (hr) e[6] += fabs((double)a.u[(3 + k) * ps + i + 1] - T[k]);
-            if (hd) e[6] += fabs((double)a.u[(3 + k) * ps + i + W] - T[k]);
+            if (hr) e[6] += fabs((double)ur[3 + k] - T[k]);
+            if (hd) e[6] += fabs((double)ud[3 + k] - T[k]);
             e[7] += fmax(-T[k], 0.0);
         }
     });
@@ -1256,16 +1315,21 @@ __device__ __forceinline__ void output_body(const Args& a, const Lc& lc, const S
     if (a.scal[S_BADIN] != 0.0) return;
     const long long ps = a.ps;
     for_each_pixel(a, lc, [&](int x, int y, long long i) {
+        // every load ahead of the stores, which the compiler may not move them past
+        float uv[N], Iv[3];
+#pragma unroll
+        for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + i];
+        load3(a.I, ps, i, Iv);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float r = a.u[c * ps + i];
-            if (a.out) a.out[c * ps + i] = expf(r);
-            a.rprev[c * ps + i] = r;
-            a.Iprev[c * ps + i] = a.I[c * ps + i];
+            a.rprev[c * ps + i] = uv[c];
+            a.Iprev[c * ps + i] = Iv[c];
         }
         if (a.out) {
 #pragma unroll
-            for (int v = 3; v < N; ++v) a.out[v * ps + i] = a.u[v * ps + i];
+            for (int c = 0; c < 3; ++c) a.out[c * ps + i] = expf(uv[c]);
+#pragma unroll
+            for (int v = 3; v < N; ++v) a.out[v * ps + i] = uv[v];
         }
     });
 }
@@ -1331,7 +1395,7 @@ template <int K> constexpr int lds_waves() {
     constexpr int w = (int)((160 * 1024) / lds_pcg<K>());
     return w > 8 ? 8 : (w < 1 ? 1 : w);
 }
-template <int K> constexpr int mv_waves() { return K <= 6 ? (lds_waves<K>() < 6 ? lds_waves<K>() : 6) : 1; }
+template <int K> constexpr int mv_waves() { return K <= 8 ? (lds_waves<K>() < 6 ? lds_waves<K>() : 6) : 1; }
 #define GID_NO_ATTR(T)
 #define GID_GN_ATTR(T) __attribute__((amdgpu_waves_per_eu(4)))
 #define GID_MV_ATTR(T) __attribute__((amdgpu_waves_per_eu(mv_waves<T>())))
