@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <string>
 #include <utility>
@@ -973,13 +974,10 @@ struct gid_batch {
     std::vector<int> nb_snapshot;      // per-clip workgroup counts the batch was built with
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    void* dmem = nullptr;              // device: Args[n], then per K group its wg_pix and wg_bs prefixes
-    Args* d_args = nullptr;
-    int* d_wg = nullptr;
-    Args* h_args = nullptr;            // pinned staging of the same
-    int* h_wg = nullptr;
     double* h_out = nullptr;           // pinned: per clip final energy and input-check flag
-    std::map<std::pair<unsigned long long, int>, hipGraphExec_t> graphs;
+    // cached schedule graphs by (active clips, refine, clips with the temporal prior on):
+    // the descriptors are baked into the graph's kernel arguments
+    std::map<std::tuple<unsigned long long, int, unsigned long long>, hipGraphExec_t> graphs;
     std::vector<int> active;           // clips of the pending step
     bool pending = false;
     std::string err;
@@ -1001,9 +999,6 @@ void batch_release(gid_batch* b) {
     for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     b->graphs.clear();
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-    if (b->dmem) (void)hipFree(b->dmem);
-    if (b->h_args) (void)hipHostFree(b->h_args);
-    if (b->h_wg) (void)hipHostFree(b->h_wg);
     if (b->h_out) (void)hipHostFree(b->h_out);
 }
 }  // namespace
@@ -1029,17 +1024,11 @@ gid_status gid_batch_create(gid_ctx* const* ctxs, int32_t n, gid_batch** out) {
         b->clips.push_back(ctxs[i]);
         b->nb_snapshot.push_back(ctxs[i]->nblocks);
     }
-    const size_t args_bytes = align_up(sizeof(Args) * n, 256);
-    if (hipMalloc(&b->dmem, args_bytes + sizeof(int) * 4 * (n + 1)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&b->h_args), sizeof(Args) * n) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&b->h_wg), sizeof(int) * 4 * (n + 1)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(double) * 2 * n) != hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(double) * 2 * n) != hipSuccess) {
         batch_release(b);
         delete b;
         return GID_ERR_OUT_OF_MEMORY;
     }
-    b->d_args = static_cast<Args*>(b->dmem);
-    b->d_wg = reinterpret_cast<int*>(static_cast<char*>(b->dmem) + args_bytes);
     *out = b;
     return GID_OK;
 }
@@ -1077,47 +1066,41 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
     if (mode == GID_REFINE_FIRST_FRAME && first_count != 0 && first_count != (int)act.size())
         return bfail(b, GID_ERR_UNSUPPORTED, "refine-first-frame needs the active clips at the same frame");
     const bool refine = mode == GID_REFINE_EVERY_STEP || (mode == GID_REFINE_FIRST_FRAME && first_count > 0);
-    // active clips grouped by K (clips keep their relative order inside a group);
-    // every kernel of the step is launched once per group
+    // active clips grouped by K (clips keep their relative order inside a group),
+    // each group cut into launches of at most BATCH_LAUNCH_MAX clips; every kernel
+    // of the step is launched once per such launch
     std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return b->clips[x]->K < b->clips[y]->K; });
     const int na = (int)act.size();
     std::vector<BatchGrid> groups;
-    int* hw = b->h_wg;
-    int wofs = 0;
+    unsigned long long tmask = 0;
     for (int j = 0; j < na;) {
         const int K = b->clips[act[j]]->K;
         int m = 0;
-        while (j + m < na && b->clips[act[j + m]]->K == K) ++m;
-        int* wg_pix = hw + wofs;
-        int* wg_bs = wg_pix + (m + 1);
-        wg_pix[0] = wg_bs[0] = 0;
+        while (j + m < na && m < BATCH_LAUNCH_MAX && b->clips[act[j + m]]->K == K) ++m;
+        BatchGrid g{};
+        g.ba.n = m;
+        g.ba.wg_pix[0] = g.ba.wg_bs[0] = 0;
         for (int q = 0; q < m; ++q) {
-            gid_ctx* c = b->clips[act[j + q]];
+            const int i = act[j + q];
+            gid_ctx* c = b->clips[i];
             Args a = base_args(c);
-            a.in_frame = frames[act[j + q]];
-            a.in_ids = ids[act[j + q]];
-            a.out = layers ? layers[act[j + q]] : nullptr;
+            a.in_frame = frames[i];
+            a.in_ids = ids[i];
+            a.out = layers ? layers[i] : nullptr;
             a.first = c->frame_index == 0;
             a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
-            b->h_args[j + q] = a;
-            wg_pix[q + 1] = wg_pix[q] + c->nblocks;
-            wg_bs[q + 1] = wg_bs[q] + c->nb_bs;
+            if (a.temporal) tmask |= 1ull << i;
+            g.ba.a[q] = a;
+            g.ba.wg_pix[q + 1] = g.ba.wg_pix[q] + c->nblocks;
+            g.ba.wg_bs[q + 1] = g.ba.wg_bs[q] + c->nb_bs;
         }
-        BatchGrid g;
-        g.args = b->d_args + j;
-        g.wg_pix = b->d_wg + wofs;
-        g.wg_bs = b->d_wg + wofs + (m + 1);
-        g.nclips = m;
-        g.total_pix = wg_pix[m];
-        g.total_bs = wg_bs[m];
+        g.total_pix = g.ba.wg_pix[m];
+        g.total_bs = g.ba.wg_bs[m];
         g.k = K;
         groups.push_back(g);
-        wofs += 2 * (m + 1);
         j += m;
     }
     hipStream_t st = b->stream;
-    GID_BHIP(b, hipMemcpyAsync(b->d_args, b->h_args, sizeof(Args) * na, hipMemcpyHostToDevice, st));
-    GID_BHIP(b, hipMemcpyAsync(b->d_wg, b->h_wg, sizeof(int) * wofs, hipMemcpyHostToDevice, st));
     auto each = [&](Kern k, const Step& s, hipStream_t cs) {
         for (const BatchGrid& g : groups) {
             const hipError_t e = launch_batch(k, g, s, cs);
@@ -1136,7 +1119,7 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
                                 [&](Kern k, const Step& s) { return each(k, s, cs); }, &ns);
     };
     if (prm.use_graph) {
-        const auto key = std::make_pair(mask, refine ? 1 : 0);
+        const auto key = std::make_tuple(mask, refine ? 1 : 0, tmask);
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
             hipGraphExec_t ex = nullptr;

@@ -65,8 +65,8 @@ struct Step {
 };
 
 // One clip: its geometry, parameters and every buffer a kernel may touch.
-// Passed by value to single-clip launches; kept in device memory (one per clip)
-// for batched launches.
+// Passed by value to single-clip launches and, up to BATCH_LAUNCH_MAX of them,
+// inside a BatchArgs to batched launches.
 struct Args {
     int W, H, K;
     int ppt;                 // pixel rows per thread (tile height = TYW * ppt)
@@ -128,13 +128,22 @@ enum Kern : int {
     KN_ENERGY, KN_ENERGY_FINISH, KN_OUTPUT, KN_TABLES, KN_CAND_TABLES, KN_JUDGE
 };
 
-// A batched launch over several clips: per-clip descriptors in device memory and
-// device prefix tables of the per-clip workgroup counts (each a multiple of 8).
+// A batched launch over several clips of one K.  The descriptors travel as a
+// kernel argument (kernel arguments are read with scalar loads and pointers read
+// from them are known to be global, so the kernels keep the single-clip code);
+// wg_pix / wg_bs are prefix sums of the per-clip workgroup counts (each a
+// multiple of 8) of the per-pixel and of the apply + base-colour-sum launches.
+constexpr int BATCH_LAUNCH_MAX = 8;
+struct BatchArgs {
+    Args a[BATCH_LAUNCH_MAX];
+    int wg_pix[BATCH_LAUNCH_MAX + 1];
+    int wg_bs[BATCH_LAUNCH_MAX + 1];
+    int n;
+};
+static_assert(sizeof(BatchArgs) + sizeof(Step) <= 4096, "kernel arguments are limited to 4 KB");
+
 struct BatchGrid {
-    const Args* args;
-    const int* wg_pix;      // per-pixel launches
-    const int* wg_bs;       // apply + base-colour-sum launches
-    int nclips;
+    BatchArgs ba;
     int total_pix, total_bs;
     int k;                  // the K every clip of this launch has
 };

@@ -1371,20 +1371,17 @@ __device__ __forceinline__ Lc clip_grid(const int* wg, int c) {
     return Lc{xcd_order((int)blockIdx.x - wg[c], nb), nb};
 }
 
-#define GID_PIXEL_KERNELS(NAME, ATTR)                                                              \
+#define GID_PIXEL_KERNELS(NAME, ATTR, WG)                                                          \
     template <int K>                                                                               \
     __global__ __launch_bounds__(NTHREADS) ATTR(K) void k_##NAME(Args a, Step st) {                \
         extern __shared__ __align__(16) char smem[];                                               \
         NAME##_body<K>(a, whole_grid(), st, smem);                                                 \
     }                                                                                              \
     template <int KB>                                                                              \
-    __global__ __launch_bounds__(NTHREADS) ATTR(KB) void kb_##NAME(const Args* __restrict__ args, const int* wg,  \
-                                                                   int nclips, Step st) {          \
+    __global__ __launch_bounds__(NTHREADS) ATTR(KB) void kb_##NAME(const BatchArgs ba, Step st) {  \
         extern __shared__ __align__(16) char smem[];                                               \
-        const int c = clip_index(wg, nclips);                                                      \
-        const Args& a = args[c];                                                                   \
-        const Lc lc = clip_grid(wg, c);                                                            \
-        NAME##_body<KB>(a, lc, st, smem);                                                          \
+        const int c = clip_index(ba.WG, ba.n);                                                     \
+        NAME##_body<KB>(ba.a[c], clip_grid(ba.WG, c), st, smem);                                   \
     }
 
 // Occupancy targets.  The PCG iteration's LDS tile limits a CU to lds_waves<K>()
@@ -1400,21 +1397,21 @@ template <int K> constexpr int mv_waves() { return K <= 8 ? (lds_waves<K>() < 6 
 #define GID_GN_ATTR(T) __attribute__((amdgpu_waves_per_eu(4)))
 #define GID_MV_ATTR(T) __attribute__((amdgpu_waves_per_eu(mv_waves<T>())))
 
-GID_PIXEL_KERNELS(precompute, GID_NO_ATTR)
-GID_PIXEL_KERNELS(gn_build, GID_GN_ATTR)
-GID_PIXEL_KERNELS(pcg, GID_MV_ATTR)
-GID_PIXEL_KERNELS(apply_bsum, GID_NO_ATTR)
-GID_PIXEL_KERNELS(energy, GID_NO_ATTR)
-GID_PIXEL_KERNELS(output, GID_NO_ATTR)
+GID_PIXEL_KERNELS(precompute, GID_NO_ATTR, wg_pix)
+GID_PIXEL_KERNELS(gn_build, GID_GN_ATTR, wg_pix)
+GID_PIXEL_KERNELS(pcg, GID_MV_ATTR, wg_pix)
+GID_PIXEL_KERNELS(apply_bsum, GID_NO_ATTR, wg_bs)
+GID_PIXEL_KERNELS(energy, GID_NO_ATTR, wg_pix)
+GID_PIXEL_KERNELS(output, GID_NO_ATTR, wg_pix)
 
 __global__ __launch_bounds__(NTHREADS) void k_scan(Args a, Step st) {
     extern __shared__ __align__(16) char smem[];
     scan_body(a, whole_grid(), st, smem);
 }
-__global__ __launch_bounds__(NTHREADS) void kb_scan(const Args* args, const int* wg, int nclips, Step st) {
+__global__ __launch_bounds__(NTHREADS) void kb_scan(const BatchArgs ba, Step st) {
     extern __shared__ __align__(16) char smem[];
-    const int c = clip_index(wg, nclips);
-    scan_body(args[c], clip_grid(wg, c), st, smem);
+    const int c = clip_index(ba.wg_pix, ba.n);
+    scan_body(ba.a[c], clip_grid(ba.wg_pix, c), st, smem);
 }
 
 // one workgroup per clip
@@ -1424,24 +1421,23 @@ __global__ __launch_bounds__(BSOLVE_THREADS) void k_bsolve(Args a, Step st) {
     bsolve_body<K>(a, Lc{0, 1}, st, smem);
 }
 template <int KB>
-__global__ __launch_bounds__(BSOLVE_THREADS) void kb_bsolve(const Args* args, Step st) {
+__global__ __launch_bounds__(BSOLVE_THREADS) void kb_bsolve(const BatchArgs ba, Step st) {
     extern __shared__ __align__(16) char smem[];
-    const Args& a = args[blockIdx.x];
-    bsolve_body<KB>(a, Lc{0, 1}, st, smem);
+    bsolve_body<KB>(ba.a[blockIdx.x], Lc{0, 1}, st, smem);
 }
 __global__ __launch_bounds__(NTHREADS) void k_energy_finish(Args a, Step st) {
     extern __shared__ __align__(16) char smem[];
     energy_finish_body(a, Lc{0, 1}, st, smem);
 }
-__global__ __launch_bounds__(NTHREADS) void kb_energy_finish(const Args* args, Step st) {
+__global__ __launch_bounds__(NTHREADS) void kb_energy_finish(const BatchArgs ba, Step st) {
     extern __shared__ __align__(16) char smem[];
-    energy_finish_body(args[blockIdx.x], Lc{0, 1}, st, smem);
+    energy_finish_body(ba.a[blockIdx.x], Lc{0, 1}, st, smem);
 }
 __global__ void k_reset_frame(Args a, Step st) { reset_frame_body(a, Lc{0, 1}, st, nullptr); }
 __global__ void k_tables(Args a, Step st) { tables_body(a, Lc{0, 1}, st, nullptr); }
 __global__ void k_cand_tables(Args a, Step st) { cand_tables_body(a, Lc{0, 1}, st, nullptr); }
 __global__ __launch_bounds__(NTHREADS) void k_judge(Args a, Step st) { judge_body(a, whole_grid(), st, nullptr); }
-__global__ void kb_reset_frame(const Args* args, Step st) { reset_frame_body(args[blockIdx.x], Lc{0, 1}, st, nullptr); }
+__global__ void kb_reset_frame(const BatchArgs ba, Step st) { reset_frame_body(ba.a[blockIdx.x], Lc{0, 1}, st, nullptr); }
 
 }  // namespace
 
@@ -1505,16 +1501,16 @@ hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
 }
 
 hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t s) {
-    const dim3 blk(NTHREADS), gpix(g.total_pix), gbs(g.total_bs), gone(g.nclips);
+    const dim3 blk(NTHREADS), gpix(g.total_pix), gbs(g.total_bs), gone(g.ba.n);
     switch (k) {
         case KN_SCAN:
-            hipLaunchKernelGGL(kb_scan, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+            hipLaunchKernelGGL(kb_scan, gpix, blk, LDS_SMALL, s, g.ba, st);
             return hipGetLastError();
         case KN_RESET:
-            hipLaunchKernelGGL(kb_reset_frame, gone, dim3(64), 0, s, g.args, st);
+            hipLaunchKernelGGL(kb_reset_frame, gone, dim3(64), 0, s, g.ba, st);
             return hipGetLastError();
         case KN_ENERGY_FINISH:
-            hipLaunchKernelGGL(kb_energy_finish, gone, blk, LDS_SMALL, s, g.args, st);
+            hipLaunchKernelGGL(kb_energy_finish, gone, blk, LDS_SMALL, s, g.ba, st);
             return hipGetLastError();
         default:
             break;
@@ -1523,25 +1519,25 @@ hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t 
         constexpr int KB = decltype(kc)::value;
         switch (k) {
             case KN_PRECOMPUTE:
-                hipLaunchKernelGGL(kb_precompute<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+                hipLaunchKernelGGL(kb_precompute<KB>, gpix, blk, LDS_SMALL, s, g.ba, st);
                 break;
             case KN_GN_BUILD:
-                hipLaunchKernelGGL(kb_gn_build<KB>, gpix, blk, lds_gn_build<KB>(), s, g.args, g.wg_pix, g.nclips, st);
+                hipLaunchKernelGGL(kb_gn_build<KB>, gpix, blk, lds_gn_build<KB>(), s, g.ba, st);
                 break;
             case KN_PCG:
-                hipLaunchKernelGGL(kb_pcg<KB>, gpix, blk, lds_pcg<KB>(), s, g.args, g.wg_pix, g.nclips, st);
+                hipLaunchKernelGGL(kb_pcg<KB>, gpix, blk, lds_pcg<KB>(), s, g.ba, st);
                 break;
             case KN_APPLY_BSUM:
-                hipLaunchKernelGGL(kb_apply_bsum<KB>, gbs, blk, lds_apply_bsum<KB>(), s, g.args, g.wg_bs, g.nclips, st);
+                hipLaunchKernelGGL(kb_apply_bsum<KB>, gbs, blk, lds_apply_bsum<KB>(), s, g.ba, st);
                 break;
             case KN_BSOLVE:
-                hipLaunchKernelGGL(kb_bsolve<KB>, gone, dim3(BSOLVE_THREADS), lds_bsolve<KB>(), s, g.args, st);
+                hipLaunchKernelGGL(kb_bsolve<KB>, gone, dim3(BSOLVE_THREADS), lds_bsolve<KB>(), s, g.ba, st);
                 break;
             case KN_ENERGY:
-                hipLaunchKernelGGL(kb_energy<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+                hipLaunchKernelGGL(kb_energy<KB>, gpix, blk, LDS_SMALL, s, g.ba, st);
                 break;
             case KN_OUTPUT:
-                hipLaunchKernelGGL(kb_output<KB>, gpix, blk, LDS_SMALL, s, g.args, g.wg_pix, g.nclips, st);
+                hipLaunchKernelGGL(kb_output<KB>, gpix, blk, LDS_SMALL, s, g.ba, st);
                 break;
             default: break;
         }
