@@ -619,37 +619,46 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
 #pragma unroll
             for (int v = 0; v < N; ++v) Ul[v * HN + li] = own_in ? uv[v] : 0.0f;
         }
+        // z and M^-1 of the own pixel, held through the stencil for the iteration's sums
+        float zk[N], mk[N];
         if (dbg || first) {
             float pv[N];
 #pragma unroll
             for (int v = 0; v < N; ++v) pv[v] = pold[v * ps + io];
             if (!dbg) {
-                float rv[N], mv[N];
+                float rv[N];
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
                     rv[v] = rold[v * ps + io];
-                    mv[v] = a.minv[v * ps + io];
+                    mk[v] = a.minv[v * ps + io];
                 }
 #pragma unroll
-                for (int v = 0; v < N; ++v) acc[PV_RZ] += own_in ? (double)rv[v] * (double)(rv[v] * mv[v]) : 0.0;
+                for (int v = 0; v < N; ++v) {
+                    zk[v] = rv[v] * mk[v];
+                    acc[PV_RZ] += own_in ? (double)rv[v] * (double)zk[v] : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < N; ++v) zk[v] = mk[v] = 0.0f;
             }
 #pragma unroll
             for (int v = 0; v < N; ++v) Pl[v * HN + li] = own_in ? pv[v] : 0.0f;
         } else {
-            float po[N], rv[N], qv[N], mv[N], xv[N];
+            float po[N], rv[N], qv[N], xv[N];
 #pragma unroll
             for (int v = 0; v < N; ++v) {
                 const long long j = v * ps + io;
                 po[v] = pold[j];
                 rv[v] = rold[j];
                 qv[v] = qold[j];
-                mv[v] = a.minv[j];
+                mk[v] = a.minv[j];
                 xv[v] = a.delta[j];
             }
 #pragma unroll
             for (int v = 0; v < N; ++v) {
                 const float r = (float)((double)rv[v] - alpha * (double)qv[v]);
-                const float z = r * mv[v];
+                const float z = r * mk[v];
+                zk[v] = z;
                 const float p = fmaf(betaf, po[v], z);
                 xv[v] = (float)((double)xv[v] + alpha * (double)po[v]);
                 rv[v] = r;
@@ -779,22 +788,12 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
 #pragma unroll
                 for (int v = 0; v < N; ++v) qcur[v * ps + i] = q[v];
             } else {
-                // r_i and M^-1 read again (this thread wrote r_i) rather than held
-                // through the stencil; all loads ahead of the q stores, which the
-                // compiler may not move them past
-                float rv[N], mv[N];
-#pragma unroll
-                for (int v = 0; v < N; ++v) {
-                    rv[v] = rcur[v * ps + i];
-                    mv[v] = a.minv[v * ps + i];
-                }
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
                     qcur[v * ps + i] = q[v];
-                    const float z = rv[v] * mv[v];
                     acc[PV_PQ] += (double)p[v] * (double)q[v];
-                    acc[PV_QZ] += (double)q[v] * (double)z;
-                    acc[PV_QMQ] += (double)q[v] * (double)(q[v] * mv[v]);
+                    acc[PV_QZ] += (double)q[v] * (double)zk[v];
+                    acc[PV_QMQ] += (double)q[v] * (double)(q[v] * mk[v]);
                 }
             }
         }
@@ -1385,14 +1384,18 @@ __device__ __forceinline__ Lc clip_grid(const int* wg, int c) {
     }
 
 // Occupancy targets.  The PCG iteration's LDS tile limits a CU to lds_waves<K>()
-// workgroups (one wavefront of each per SIMD).  For K <= 6 the allocator is held
-// to that occupancy, at most six waves per SIMD (below 80 registers the small-K
-// kernels spill); for larger K the natural allocation is kept.
+// workgroups (one wavefront of each per SIMD).  For K <= 8 the allocator is held
+// to that occupancy, at most six waves per SIMD for K <= 3 and five above (the
+// registers that the PCG iteration holds through its stencil do not fit the 80 of
+// six waves from K = 4 on); for larger K the natural allocation is kept.
 template <int K> constexpr int lds_waves() {
     constexpr int w = (int)((160 * 1024) / lds_pcg<K>());
     return w > 8 ? 8 : (w < 1 ? 1 : w);
 }
-template <int K> constexpr int mv_waves() { return K <= 8 ? (lds_waves<K>() < 6 ? lds_waves<K>() : 6) : 1; }
+template <int K> constexpr int mv_waves() {
+    constexpr int cap = K <= 3 ? 6 : 5;
+    return K <= 8 ? (lds_waves<K>() < cap ? lds_waves<K>() : cap) : 1;
+}
 #define GID_NO_ATTR(T)
 #define GID_GN_ATTR(T) __attribute__((amdgpu_waves_per_eu(4)))
 #define GID_MV_ATTR(T) __attribute__((amdgpu_waves_per_eu(mv_waves<T>())))
