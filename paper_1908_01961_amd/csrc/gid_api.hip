@@ -23,6 +23,7 @@ namespace {
 
 constexpr int FINAL_SLOT = ELOG_SLOTS - 2;   // energy of the frame when half-steps are not recorded
 constexpr int PROBE_SLOT = ELOG_SLOTS - 1;   // single-step energy evaluation
+constexpr int NSTATS = NSCAL + ELOG_SLOTS * ELOG_STRIDE + 3 * KMAX;   // doubles of the statistics block
 constexpr int NB_MAX = 2048;                 // default cap on workgroups of a per-pixel launch (one tile each up to here)
 static_assert(NB_MAX <= NB_TUNE_MAX, "site totals unroll their loads up to NB_TUNE_MAX workgroups");
 constexpr uint32_t STATE_MAGIC = 0x67696431u; // "gid1"
@@ -395,9 +396,7 @@ void release(gid_ctx* c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     c->cap_stream = nullptr;
     if (c->arena) (void)hipFree(c->arena);
-    if (c->h_scal) (void)hipHostFree(c->h_scal);
-    if (c->h_elog) (void)hipHostFree(c->h_elog);
-    if (c->h_b64) (void)hipHostFree(c->h_b64);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);   // h_elog and h_b64 point into the same block
     if (c->h_small) (void)hipHostFree(c->h_small);
     if (c->warena) (void)hipFree(c->warena);
     c->warena = nullptr;
@@ -486,12 +485,11 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     const size_t o_bf = take(sizeof(float) * 3 * KMAX);
     const size_t o_lnb = take(sizeof(float) * 3 * KMAX);
     const size_t o_bcf = take(sizeof(float) * 3 * KMAX);
-    const size_t o_b64 = take(sizeof(double) * 3 * KMAX);
+    // scalars, energy log and FP64 colours back to back: one copy returns a frame's statistics
+    const size_t o_stats = take(sizeof(double) * NSTATS);
     const size_t o_lnb64 = take(sizeof(double) * 3 * KMAX);
     const size_t o_binit = take(sizeof(double) * 3 * KMAX);
-    const size_t o_scal = take(sizeof(double) * NSCAL);
     const size_t o_tick = take(sizeof(unsigned) * NRED);
-    const size_t o_elog = take(sizeof(double) * ELOG_SLOTS * ELOG_STRIDE);
     const size_t o_bsum = take(sizeof(double) * bstep_nsums(KMAX));
     const size_t o_part = take(sizeof(double) * (size_t)c->part_stride * NRED);
     if (hipMalloc(&c->arena, off) != hipSuccess) {
@@ -518,22 +516,22 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     c->bf = reinterpret_cast<float*>(base + o_bf);
     c->lnb = reinterpret_cast<float*>(base + o_lnb);
     c->bcf = reinterpret_cast<float*>(base + o_bcf);
-    c->b64 = reinterpret_cast<double*>(base + o_b64);
+    c->scal = reinterpret_cast<double*>(base + o_stats);
+    c->elog = c->scal + NSCAL;
+    c->b64 = c->elog + ELOG_SLOTS * ELOG_STRIDE;
     c->lnb64 = reinterpret_cast<double*>(base + o_lnb64);
     c->binit64 = reinterpret_cast<double*>(base + o_binit);
-    c->scal = reinterpret_cast<double*>(base + o_scal);
     c->tickets = reinterpret_cast<unsigned*>(base + o_tick);
-    c->elog = reinterpret_cast<double*>(base + o_elog);
     c->bsum = reinterpret_cast<double*>(base + o_bsum);
     c->partials = reinterpret_cast<double*>(base + o_part);
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_scal), sizeof(double) * NSCAL) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->h_elog), sizeof(double) * ELOG_SLOTS * ELOG_STRIDE) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->h_b64), sizeof(double) * 3 * KMAX) != hipSuccess ||
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_scal), sizeof(double) * NSTATS) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_small), sizeof(double) * 8 * 3 * KMAX) != hipSuccess) {
         release(c);
         delete c;
         return GID_ERR_OUT_OF_MEMORY;
     }
+    c->h_elog = c->h_scal + NSCAL;
+    c->h_b64 = c->h_elog + ELOG_SLOTS * ELOG_STRIDE;
     // zero the whole workspace once (tickets must start at zero)
     if (hipMemsetAsync(c->arena, 0, off, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         release(c);
@@ -661,10 +659,7 @@ gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* id
     Args o = a;
     o.out = layers;
     GID_HIP(c, L1(c, c->stream, KN_OUTPUT, o, Step{}));
-    GID_HIP(c, hipMemcpyAsync(c->h_elog, c->elog, sizeof(double) * ELOG_SLOTS * ELOG_STRIDE, hipMemcpyDeviceToHost,
-                              c->stream));
-    GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSCAL, hipMemcpyDeviceToHost, c->stream));
-    GID_HIP(c, hipMemcpyAsync(c->h_b64, c->b64, sizeof(double) * 3 * c->K, hipMemcpyDeviceToHost, c->stream));
+    GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSTATS, hipMemcpyDeviceToHost, c->stream));
     c->pending = true;
     c->pend_b = b_out;
     c->pend_stats = stats;
