@@ -91,6 +91,41 @@ def test_batch_equals_single_clips_bitwise(torch):
         s.close()
 
 
+def test_batch_of_one_K_splits_into_launches_bitwise(torch):
+    """Eleven clips of one K: a step issues two launches (eight clips, then three);
+    clips that end early change the active set and the temporal flags between
+    steps.  Every clip equals its single-clip run bit for bit."""
+    import paper_1908_01961_amd as G
+    sizes = [(40, 24), (64, 16), (72, 40), (48, 48), (96, 20), (33, 17), (64, 64), (80, 36),
+             (56, 30), (100, 12), (45, 45)]
+    clips = [make_clip(W, H, 4, 2 + (j % 3), 420 + j) for j, (W, H) in enumerate(sizes)]
+    _say("batch of one K:", [(c.width, c.height, c.nframes) for c in clips])
+    single = []
+    for c in clips:
+        s = _solver(c)
+        lay = torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda")
+        out = []
+        for t in range(c.nframes):
+            _, st = s.decompose_frame(_dev(torch, c.frames[t]), _dev(torch, c.ids[t]), lay)
+            out.append((lay.cpu().numpy().copy(), st["energy_final"]))
+        s.close()
+        single.append(out)
+    solvers = [_solver(c) for c in clips]
+    batch = G.Batch(solvers)
+    lays = [torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda") for c in clips]
+    for t in range(max(c.nframes for c in clips)):
+        frames = [_dev(torch, c.frames[t]) if t < c.nframes else None for c in clips]
+        ids = [_dev(torch, c.ids[t]) if t < c.nframes else None for c in clips]
+        e = batch.step(frames, ids, lays)
+        for i, c in enumerate(clips):
+            if t < c.nframes:
+                assert np.array_equal(lays[i].cpu().numpy(), single[i][t][0]), (i, t)
+                assert e[i] == single[i][t][1], (i, t)
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
 def test_batch_first_frames_match_oracle(torch):
     import paper_1908_01961_amd as G
     clips = _clips()
