@@ -192,7 +192,9 @@ gid_status gid_base_step(gid_ctx *ctx, int32_t *accepted);
 /* ---- kernel timing ----
  * With profiling on, the following solves launch kernels directly (no graph)
  * with a HIP event pair around every launch on the context's stream; the
- * elapsed times are accumulated per kernel kind at gid_synchronize. */
+ * elapsed times are accumulated per kernel kind at gid_synchronize.
+ * GID_KERNEL_PCG is one Jacobi-PCG iteration (vector updates fused with the
+ * J^T J product, Sec. 6.1), launched pcg_iters times per layer step. */
 enum {
     GID_KERNEL_SCAN = 0, GID_KERNEL_PRECOMPUTE, GID_KERNEL_GN_BUILD, GID_KERNEL_PCG,
     GID_KERNEL_APPLY_BSUM, GID_KERNEL_BSOLVE, GID_KERNEL_ENERGY, GID_KERNEL_OUTPUT,
@@ -207,10 +209,12 @@ gid_status gid_get_kernel_times(gid_ctx *ctx, double *ms_out, int64_t *launches_
 /* ---- batches of clips of uneven size ----
  * A batch groups contexts (each with its own frame size and K) that share the
  * stream, the schedule (gn_iters, pcg_iters, refine_mode) and record_energy = 0.
- * Every kernel of a batch step is one launch over all active clips: each
- * workgroup finds its clip in a device descriptor table and runs that clip's
- * kernel body; reductions stay per clip.  With use_graph the outer iterations
- * of a step are replayed from a graph cached per set of active clips. */
+ * Every kernel of a batch step is one launch per K among the active clips (per
+ * eight clips of one K): each workgroup finds its clip from a prefix table of
+ * workgroup counts and runs that clip's kernel body, the clip descriptors
+ * travelling in the kernel arguments; reductions stay per clip.  With use_graph
+ * the outer iterations of a step are replayed from a graph cached per set of
+ * active clips, refinement and set of clips with the temporal prior on. */
 typedef struct gid_batch gid_batch;
 
 /* Group n (1..64) distinct contexts into a batch.  Tune the contexts (gid_autotune,
