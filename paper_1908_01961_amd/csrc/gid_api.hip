@@ -40,7 +40,7 @@ struct gid_ctx {
     int device = 0;
     void* arena = nullptr;
     // device workspace
-    float *u = nullptr, *delta = nullptr, *rA = nullptr, *rB = nullptr, *pA = nullptr, *pB = nullptr, *qA = nullptr, *qB = nullptr,
+    float *u = nullptr, *delta = nullptr, *zA = nullptr, *zB = nullptr, *pA = nullptr, *pB = nullptr, *qA = nullptr, *qB = nullptr,
           *minv = nullptr, *I = nullptr, *wsr = nullptr, *tg = nullptr, *Iprev = nullptr,
           *rprev = nullptr, *bf = nullptr, *lnb = nullptr, *bcf = nullptr;
     uint8_t* ids = nullptr;
@@ -189,8 +189,8 @@ Args base_args(const gid_ctx* c) {
     a.cr_literal = c->prm.cr_mode == GID_CR_LITERAL;
     a.u = c->u;
     a.delta = c->delta;
-    a.rA = c->rA;
-    a.rB = c->rB;
+    a.zA = c->zA;
+    a.zB = c->zB;
     a.pA = c->pA;
     a.pB = c->pB;
     a.qA = c->qA;
@@ -477,8 +477,8 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
         return o;
     };
     const size_t fplane = sizeof(float) * (size_t)c->ps;
-    const size_t o_u = take(fplane * c->n), o_delta = take(fplane * c->n), o_rA = take(fplane * c->n),
-                 o_rB = take(fplane * c->n), o_pA = take(fplane * c->n), o_pB = take(fplane * c->n),
+    const size_t o_u = take(fplane * c->n), o_delta = take(fplane * c->n), o_zA = take(fplane * c->n),
+                 o_zB = take(fplane * c->n), o_pA = take(fplane * c->n), o_pB = take(fplane * c->n),
                  o_qA = take(fplane * c->n), o_qB = take(fplane * c->n), o_minv = take(fplane * c->n), o_I = take(fplane * 3), o_wsr = take(fplane),
                  o_tg = take(fplane * 4), o_Iprev = take(fplane * 3), o_rprev = take(fplane * 3);
     const size_t o_ids = take((size_t)c->ps);
@@ -500,8 +500,8 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     auto fp = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
     c->u = fp(o_u);
     c->delta = fp(o_delta);
-    c->rA = fp(o_rA);
-    c->rB = fp(o_rB);
+    c->zA = fp(o_zA);
+    c->zB = fp(o_zB);
     c->pA = fp(o_pA);
     c->pB = fp(o_pB);
     c->qA = fp(o_qA);

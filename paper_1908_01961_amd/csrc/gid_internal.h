@@ -80,12 +80,12 @@ struct Args {
     int cr_literal;
     float* u;                // n planes
     float* delta;            // x: the layer step accumulated by PCG
-    float* rA;               // residual r, even PCG iterations (and r0)
-    float* rB;               // residual r, odd iterations
+    float* zA;               // preconditioned residual z = M^-1 r, even PCG iterations from 2
+    float* zB;               // z, odd iterations (z0 = p0 lives in pA)
     float* pA;               // search direction, even iterations (and p0)
     float* pB;               // search direction, odd iterations
-    float* qA;               // q = A p, even iterations
-    float* qB;               // q = A p, odd iterations
+    float* qA;               // M^-1 q with q = A p, even iterations
+    float* qB;               // M^-1 q, odd iterations
     float* minv;             // Jacobi preconditioner M^-1 (inverse diagonal of A)
     float* I;                // 3 planes (frame copy)
     uint8_t* ids;

@@ -128,11 +128,11 @@ __device__ __forceinline__ void block_sums(double* v, double* sh) {
     for (int j = 0; j < NV; ++j) v[j] = (sh[j] + sh[NV + j]) + (sh[2 * NV + j] + sh[3 * NV + j]);
 }
 
-// PCG vectors of iteration i (ping-pong by parity; the build writes r0 and p0
-// into the even buffers).
+// PCG vectors of iteration i (ping-pong by parity; the build writes p0 = z0 into
+// the even p buffer).
 __device__ __forceinline__ int pcg_site(int i) { return (i & 1) ? R_PCGB : R_PCGA; }
 __device__ __forceinline__ float* p_buf(const Args& a, int i) { return (i & 1) ? a.pB : a.pA; }
-__device__ __forceinline__ float* r_buf(const Args& a, int i) { return (i & 1) ? a.rB : a.rA; }
+__device__ __forceinline__ float* z_buf(const Args& a, int i) { return (i & 1) ? a.zB : a.zA; }
 __device__ __forceinline__ float* q_buf(const Args& a, int i) { return (i & 1) ? a.qB : a.qA; }
 
 // The step length of PCG iteration i and the preconditioned residual norm that
@@ -515,7 +515,6 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
                 for (int v = 0; v < N; ++v) {
                     const float mi = 1.0f / M[v];
                     const float z = g[v] * mi;
-                    a.rA[v * ps + i] = g[v];
                     a.minv[v * ps + i] = mi;
                     a.pA[v * ps + i] = z;
                     a.delta[v * ps + i] = 0.0f;
@@ -534,16 +533,20 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
 // ------------------------------------------------------------ PCG iteration
 
 // One Jacobi-PCG iteration i of the layer step per launch, the standard
-// recurrence rearranged so that it needs one grid-wide reduction per iteration:
+// recurrence rearranged so that it needs one grid-wide reduction per iteration
+// and carried in preconditioned form (z = M^-1 r and M^-1 q are stored instead
+// of r and q, so the halo needs no M^-1):
 //   i > 0: alpha_{i-1}, beta_{i-1} from the sums of iteration i-1, then
-//          x += alpha p_{i-1},  r_i = r_{i-1} - alpha q_{i-1},  z_i = M^-1 r_i,
+//          x += alpha p_{i-1},  z_i = z_{i-1} - alpha M^-1 q_{i-1},
 //          p_i = z_i + beta p_{i-1};
-//   all:   q_i = A p_i (J^T W J applied matrix-free from the unknowns), and the
-//          sums <p_i, q_i>, <q_i, z_i>, <q_i, M^-1 q_i>, <r_i, z_i>.
+//   all:   q_i = A p_i (J^T W J applied matrix-free from the unknowns), M^-1 q_i
+//          stored, and the sums <p_i, q_i>, <q_i, z_i>, <q_i, M^-1 q_i>,
+//          <r_i, z_i> (r_i = z_i / M^-1).
 // The vector updates are FP32 (the two axpys through FP64, rounded once); p_i
 // is recomputed identically on the one-pixel halo of the tile, so the staged
-// search direction needs no separate pass.  The last iteration's x update is
-// applied by the apply pass.  Debug launches apply A to a caller vector.
+// search direction needs no separate pass.  z0 = p0 is the build's p0.  The last
+// iteration's x update is applied by the apply pass.  Debug launches apply A to
+// a caller vector.
 constexpr int NHALO = 2 * HW + 2 * TYW;   // halo elements of a 64 x 4 tile
 static_assert(NHALO <= NTHREADS, "one halo element per thread");
 
@@ -580,10 +583,10 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
         betaf = ps_.rz_next > 0.0 ? (float)(ps_.rz_next / ps_.rz) : 0.0f;
     }
     const float* pold = dbg ? a.pdebug : p_buf(a, first ? 0 : it - 1);
-    const float* rold = r_buf(a, first ? 0 : it - 1);
-    const float* qold = q_buf(a, it - 1);
+    const float* zold = it <= 1 ? a.pA : z_buf(a, it - 1);     // z0 = p0
+    const float* qold = q_buf(a, it - 1);                        // M^-1 q of iteration it-1
     float* pcur = p_buf(a, it);
-    float* rcur = r_buf(a, it);
+    float* zcur = z_buf(a, it);
     float* qcur = dbg ? a.out : q_buf(a, it);
     const Lam L = a.lam;
     const long long ps = a.ps;
@@ -626,16 +629,12 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
 #pragma unroll
             for (int v = 0; v < N; ++v) pv[v] = pold[v * ps + io];
             if (!dbg) {
-                float rv[N];
+#pragma unroll
+                for (int v = 0; v < N; ++v) mk[v] = a.minv[v * ps + io];
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
-                    rv[v] = rold[v * ps + io];
-                    mk[v] = a.minv[v * ps + io];
-                }
-#pragma unroll
-                for (int v = 0; v < N; ++v) {
-                    zk[v] = rv[v] * mk[v];
-                    acc[PV_RZ] += own_in ? (double)rv[v] * (double)zk[v] : 0.0;
+                    zk[v] = pv[v];                     // z0 = p0
+                    acc[PV_RZ] += own_in ? (double)(zk[v] * rcp_pos(mk[v])) * (double)zk[v] : 0.0;
                 }
             } else {
 #pragma unroll
@@ -644,26 +643,24 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
 #pragma unroll
             for (int v = 0; v < N; ++v) Pl[v * HN + li] = own_in ? pv[v] : 0.0f;
         } else {
-            float po[N], rv[N], qv[N], xv[N];
+            float po[N], zv[N], qv[N], xv[N];
 #pragma unroll
             for (int v = 0; v < N; ++v) {
                 const long long j = v * ps + io;
                 po[v] = pold[j];
-                rv[v] = rold[j];
+                zv[v] = zold[j];
                 qv[v] = qold[j];
                 mk[v] = a.minv[j];
                 xv[v] = a.delta[j];
             }
 #pragma unroll
             for (int v = 0; v < N; ++v) {
-                const float r = (float)((double)rv[v] - alpha * (double)qv[v]);
-                const float z = r * mk[v];
+                const float z = (float)((double)zv[v] - alpha * (double)qv[v]);
                 zk[v] = z;
                 const float p = fmaf(betaf, po[v], z);
                 xv[v] = (float)((double)xv[v] + alpha * (double)po[v]);
-                rv[v] = r;
                 po[v] = p;
-                acc[PV_RZ] += own_in ? (double)r * (double)z : 0.0;
+                acc[PV_RZ] += own_in ? (double)(z * rcp_pos(mk[v])) * (double)z : 0.0;   // r = z / M^-1
                 Pl[v * HN + li] = own_in ? p : 0.0f;
             }
             if (own_in) {
@@ -671,7 +668,7 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
                 for (int v = 0; v < N; ++v) {
                     const long long j = v * ps + i;
                     a.delta[j] = xv[v];
-                    rcur[j] = rv[v];
+                    zcur[j] = zk[v];
                     pcur[j] = po[v];
                 }
             }
@@ -699,19 +696,18 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
 #pragma unroll
                 for (int v = 0; v < N; ++v) Pl[v * HN + e] = in ? pv[v] : 0.0f;
             } else {
-                float po[N], rv[N], qv[N], mv[N];
+                float po[N], zv[N], qv[N];
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
                     const long long j = v * ps + gi;
                     po[v] = pold[j];
-                    rv[v] = rold[j];
+                    zv[v] = zold[j];
                     qv[v] = qold[j];
-                    mv[v] = a.minv[j];
                 }
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
-                    const float r = (float)((double)rv[v] - alpha * (double)qv[v]);
-                    Pl[v * HN + e] = in ? fmaf(betaf, po[v], r * mv[v]) : 0.0f;
+                    const float z = (float)((double)zv[v] - alpha * (double)qv[v]);
+                    Pl[v * HN + e] = in ? fmaf(betaf, po[v], z) : 0.0f;
                 }
             }
         }
@@ -790,10 +786,11 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
             } else {
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
-                    qcur[v * ps + i] = q[v];
+                    const float mq = q[v] * mk[v];   // M^-1 q, what the next iteration reads
+                    qcur[v * ps + i] = mq;
                     acc[PV_PQ] += (double)p[v] * (double)q[v];
                     acc[PV_QZ] += (double)q[v] * (double)zk[v];
-                    acc[PV_QMQ] += (double)q[v] * (double)(q[v] * mk[v]);
+                    acc[PV_QMQ] += (double)q[v] * (double)mq;
                 }
             }
         }
