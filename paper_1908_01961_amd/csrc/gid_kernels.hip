@@ -681,32 +681,35 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
             const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
             const long long gi = in ? (long long)gy * W + gx : 0;
             const int e = hrow * HW + hcol;
-            {
-                float uv[N];
+            // every load of the element in one batch
+            if (first) {
+                float uv[N], pv[N];
 #pragma unroll
-                for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + gi];
+                for (int v = 0; v < N; ++v) {
+                    uv[v] = a.u[v * ps + gi];
+                    pv[v] = pold[v * ps + gi];
+                }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int v = 0; v < N; ++v) Ul[v * HN + e] = in ? uv[v] : 0.0f;
-            }
-            if (first) {
-                float pv[N];
-#pragma unroll
-                for (int v = 0; v < N; ++v) pv[v] = pold[v * ps + gi];
-#pragma unroll
-                for (int v = 0; v < N; ++v) Pl[v * HN + e] = in ? pv[v] : 0.0f;
+                for (int v = 0; v < N; ++v) {
+                    Ul[v * HN + e] = in ? uv[v] : 0.0f;
+                    Pl[v * HN + e] = in ? pv[v] : 0.0f;
+                }
             } else {
-                float po[N], zv[N], qv[N];
+                float uv[N], po[N], zv[N], qv[N];
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
                     const long long j = v * ps + gi;
+                    uv[v] = a.u[j];
                     po[v] = pold[j];
                     zv[v] = zold[j];
                     qv[v] = qold[j];
                 }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
                     const float z = (float)((double)zv[v] - alpha * (double)qv[v]);
+                    Ul[v * HN + e] = in ? uv[v] : 0.0f;
                     Pl[v * HN + e] = in ? fmaf(betaf, po[v], z) : 0.0f;
                 }
             }
