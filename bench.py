@@ -32,15 +32,15 @@ HBM_PEAK_GBS = 8000.0
 def algorithmic_bytes(n: int, tau: int, G: int, P: int) -> dict:
     """Bytes per pixel the method must move with FP32 state and the operator
     recomputed from the unknowns; the PCG vectors are carried in preconditioned
-    form (z = M^-1 r and M^-1 q).  A PCG iteration i > 0 reads u, z, M^-1 q, p, x
+    form (z = M^-1 r and M^-1 q).  A PCG iteration i > 1 reads u, z, M^-1 q, p, x
     and M^-1 (n planes each), the soft-Retinex weight and the temporal pair count,
-    and writes x, z, p and M^-1 q; the first iteration reads u, p0 (= z0) and M^-1
-    and writes M^-1 q.  The build reads u, the frame, the weight and the temporal
-    sums and writes M^-1, p0 and x; the apply reads u, x and p and writes u."""
-    it_first = 4 * n + 1 + tau
-    it_next = 10 * n + 1 + tau
-    pcg_total = it_first + (P - 1) * it_next if P > 0 else 0
-    build = 4 * n + 4 + 4 * tau
+    and writes x, z, p and M^-1 q; iteration 1 starts x from zero and reads p0 = z0
+    once; the first iteration reads u, p0 and M^-1 and writes M^-1 q.  The build
+    reads u, the frame, the weight and the temporal sums and writes M^-1 and p0;
+    the apply reads u, x and p and writes u."""
+    its = [4 * n + 1 + tau, 8 * n + 1 + tau] + [10 * n + 1 + tau] * max(0, P - 2)
+    pcg_total = sum(its[:P])
+    build = 3 * n + 4 + 4 * tau
     apply = 4 * n + 3
     return dict(pcg=4 * pcg_total / max(P, 1),            # average per PCG launch
                 frame=4 * G * (pcg_total + build + apply))

@@ -26,7 +26,8 @@ constexpr int NB_BS_MAX = 512;   // workgroups of the apply + base-colour-sum pa
 
 // Slots of the device scalar array (doubles).
 enum Scal : int {
-    S_STOP = 0,         // 1: PCG stopped by a guard (rest of the layer step is a no-op)
+    S_STOP = 0,         // nonzero: PCG stopped by a guard (rest of the layer step is a no-op);
+                        // 1 + the iteration whose launch refused the update before it (apply = P)
     S_BREAKDOWNS,   // count of PCG breakdowns this frame
     S_BREJECT,      // count of rejected base-colour steps this frame
     S_BACCEPT,      // 1 if the last base-colour step was accepted

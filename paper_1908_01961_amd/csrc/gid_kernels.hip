@@ -516,8 +516,7 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
                     const float mi = 1.0f / M[v];
                     const float z = g[v] * mi;
                     a.minv[v * ps + i] = mi;
-                    a.pA[v * ps + i] = z;
-                    a.delta[v * ps + i] = 0.0f;
+                    a.pA[v * ps + i] = z;   // x0 = 0 is not stored: iteration 1 starts from zero
                     acc += (double)g[v] * (double)z;
                 }
             }
@@ -550,7 +549,9 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
 constexpr int NHALO = 2 * HW + 2 * TYW;   // halo elements of a 64 x 4 tile
 static_assert(NHALO <= NTHREADS, "one halo element per thread");
 
-template <int K>
+// X1: iteration 1, whose x starts from x0 = 0 (the build stores no x0, so the
+// iteration neither reads x nor depends on what the buffer holds).
+template <int K, bool X1 = false>
 __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
     double* shr = reinterpret_cast<double*>(smem);             // 4 PV_N doubles
@@ -570,7 +571,7 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
         const PcgScalars ps_ = pcg_scalars(a, it - 1, lc.nb, shr);
         if (!ps_.ok) {     // breakdown guard: iteration it-1 is not applied, the layer step ends
             if (lead_thread(lc)) {
-                a.scal[S_STOP] = 1.0;
+                a.scal[S_STOP] = (double)(it + 1);
                 a.scal[S_BREAKDOWNS] += 1.0;
                 a.scal[S_RZ_LOG + (st.gn & 63)] = ps_.rz;
             }
@@ -651,7 +652,7 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
                 zv[v] = zold[j];
                 qv[v] = qold[j];
                 mk[v] = a.minv[j];
-                xv[v] = a.delta[j];
+                xv[v] = X1 ? 0.0f : a.delta[j];
             }
 #pragma unroll
             for (int v = 0; v < N; ++v) {
@@ -830,14 +831,15 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
     // u += x; without PCG iterations x is zero and <r0, z0> is logged
     double alpha = 0.0;
     bool pend = false;
-    if (st.add_delta && a.scal[S_STOP] == 0.0) {
+    const double stop0 = a.scal[S_STOP];
+    if (st.add_delta && stop0 == 0.0) {
         if (st.iter >= 0) {
             const PcgScalars ps_ = pcg_scalars(a, st.iter, a.nblocks, sh4);
             pend = ps_.ok;
             alpha = ps_.alpha;
             if (lead_thread(lc)) {
                 if (!ps_.ok) {   // breakdown guard: the iteration is not applied
-                    a.scal[S_STOP] = 1.0;
+                    a.scal[S_STOP] = (double)(st.iter + 2);
                     a.scal[S_BREAKDOWNS] += 1.0;
                 }
                 if (st.log_rz) a.scal[S_RZ_LOG + (st.gn & 63)] = ps_.ok ? ps_.rz_next : ps_.rz;
@@ -848,6 +850,12 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
         }
     }
     const float* plast = p_buf(a, st.iter < 0 ? 0 : st.iter);
+    // x is in memory once iteration 1 has run its update (x0 = 0 is never
+    // stored).  A stop value is 1 + the iteration whose launch refused the update
+    // before it (the apply pass counting as iteration P), so 3 or more means
+    // iteration 1 ran; every workgroup takes the same decision, whether or not it
+    // saw this kernel's own guard.
+    const bool xstored = stop0 == 0.0 ? st.iter >= 1 : stop0 >= 3.0;
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
     // this workgroup's contiguous chunk of tiles (XCD-aware)
@@ -889,6 +897,8 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
                         xv[v] = a.delta[v * ps + i];
                         pv[v] = plast[v * ps + i];
                     }
+#pragma unroll
+                    for (int v = 0; v < N; ++v) xv[v] = xstored ? xv[v] : 0.0f;
 #pragma unroll
                     for (int v = 0; v < N; ++v) {
                         const float x = pend ? (float)((double)xv[v] + alpha * (double)pv[v]) : xv[v];
@@ -1403,6 +1413,18 @@ template <int K> constexpr int mv_waves() {
 GID_PIXEL_KERNELS(precompute, GID_NO_ATTR, wg_pix)
 GID_PIXEL_KERNELS(gn_build, GID_GN_ATTR, wg_pix)
 GID_PIXEL_KERNELS(pcg, GID_MV_ATTR, wg_pix)
+// iteration 1 (x starts from zero)
+template <int K>
+__global__ __launch_bounds__(NTHREADS) GID_MV_ATTR(K) void k_pcg1(Args a, Step st) {
+    extern __shared__ __align__(16) char smem[];
+    pcg_body<K, true>(a, whole_grid(), st, smem);
+}
+template <int KB>
+__global__ __launch_bounds__(NTHREADS) GID_MV_ATTR(KB) void kb_pcg1(const BatchArgs ba, Step st) {
+    extern __shared__ __align__(16) char smem[];
+    const int c = clip_index(ba.wg_pix, ba.n);
+    pcg_body<KB, true>(ba.a[c], clip_grid(ba.wg_pix, c), st, smem);
+}
 GID_PIXEL_KERNELS(apply_bsum, GID_NO_ATTR, wg_bs)
 GID_PIXEL_KERNELS(energy, GID_NO_ATTR, wg_pix)
 GID_PIXEL_KERNELS(output, GID_NO_ATTR, wg_pix)
@@ -1491,7 +1513,12 @@ hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
         switch (k) {
             case KN_PRECOMPUTE: hipLaunchKernelGGL(k_precompute<KK>, grid, blk, LDS_SMALL, s, a, st); break;
             case KN_GN_BUILD: hipLaunchKernelGGL(k_gn_build<KK>, grid, blk, lds_gn_build<KK>(), s, a, st); break;
-            case KN_PCG: hipLaunchKernelGGL(k_pcg<KK>, grid, blk, lds_pcg<KK>(), s, a, st); break;
+            case KN_PCG:
+                if (st.iter == 1 && !st.debug)
+                    hipLaunchKernelGGL(k_pcg1<KK>, grid, blk, lds_pcg<KK>(), s, a, st);
+                else
+                    hipLaunchKernelGGL(k_pcg<KK>, grid, blk, lds_pcg<KK>(), s, a, st);
+                break;
             case KN_APPLY_BSUM:
                 hipLaunchKernelGGL(k_apply_bsum<KK>, dim3(a.nb_bs), blk, lds_apply_bsum<KK>(), s, a, st);
                 break;
@@ -1528,7 +1555,10 @@ hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t 
                 hipLaunchKernelGGL(kb_gn_build<KB>, gpix, blk, lds_gn_build<KB>(), s, g.ba, st);
                 break;
             case KN_PCG:
-                hipLaunchKernelGGL(kb_pcg<KB>, gpix, blk, lds_pcg<KB>(), s, g.ba, st);
+                if (st.iter == 1 && !st.debug)
+                    hipLaunchKernelGGL(kb_pcg1<KB>, gpix, blk, lds_pcg<KB>(), s, g.ba, st);
+                else
+                    hipLaunchKernelGGL(kb_pcg<KB>, gpix, blk, lds_pcg<KB>(), s, g.ba, st);
                 break;
             case KN_APPLY_BSUM:
                 hipLaunchKernelGGL(kb_apply_bsum<KB>, gbs, blk, lds_apply_bsum<KB>(), s, g.ba, st);
