@@ -480,7 +480,7 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     const size_t o_u = take(fplane * c->n), o_delta = take(fplane * c->n), o_zA = take(fplane * c->n),
                  o_zB = take(fplane * c->n), o_pA = take(fplane * c->n), o_pB = take(fplane * c->n),
                  o_qA = take(fplane * c->n), o_qB = take(fplane * c->n), o_minv = take(fplane * c->n), o_I = take(fplane * 3), o_wsr = take(fplane),
-                 o_tg = take(fplane * 4), o_Iprev = take(fplane * 3), o_rprev = take(fplane * 3);
+                 o_tg = take(fplane * 5), o_Iprev = take(fplane * 3), o_rprev = take(fplane * 3);
     const size_t o_ids = take((size_t)c->ps);
     const size_t o_bf = take(sizeof(float) * 3 * KMAX);
     const size_t o_lnb = take(sizeof(float) * 3 * KMAX);

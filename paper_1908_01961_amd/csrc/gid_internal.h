@@ -91,7 +91,8 @@ struct Args {
     float* I;                // 3 planes (frame copy)
     uint8_t* ids;
     float* wsr;              // 1 plane
-    float* tg;               // 4 planes: number of temporal pairs, sum of paired r_prev per channel
+    float* tg;               // 5 planes: number of temporal pairs, sum of paired r_prev per channel,
+                             // bit mask of the paired 3 x 3 window positions
     float* Iprev;            // 3 planes, previous frame
     float* rprev;            // 3 planes, previous frame's final r
     float* bf;               // K x 3 base colours, float

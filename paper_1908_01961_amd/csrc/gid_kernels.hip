@@ -316,6 +316,7 @@ __device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, con
         }
         a.wsr[i] = (float)(1.0 - exp(-(double)a.lam.rk * dC));
         float gsum = 0.0f, tr0 = 0.0f, tr1 = 0.0f, tr2 = 0.0f;
+        unsigned gmask = 0;   // bit k: window position k is a temporal pair
         if (a.temporal) {
             Window3 w;
             load_window3(a, x, y, i, w);
@@ -327,6 +328,7 @@ __device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, con
                     tr0 += w.r[k][0];
                     tr1 += w.r[k][1];
                     tr2 += w.r[k][2];
+                    gmask |= 1u << k;
                 }
             }
         }
@@ -334,6 +336,7 @@ __device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, con
         a.tg[ps + i] = tr0;
         a.tg[2 * ps + i] = tr1;
         a.tg[3 * ps + i] = tr2;
+        a.tg[4 * ps + i] = (float)gmask;   // exact: below 2^9
         if (a.first) {
             const double* b = a.b64 + 3 * id;
             a.u[i] = a.lnb[3 * id];
@@ -1209,7 +1212,6 @@ __device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const S
 #pragma unroll
     for (int v = 0; v < NTERMS; ++v) e[v] = 0.0;
     const double p = a.lam.p;
-    const double fl = a.lam.cfloor;
     double Bk[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -1260,17 +1262,23 @@ __device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const S
         const double gn = sqrt(g2);
         e[2] += (p == 1.0) ? gn : ((gn > 0.0) ? pow(gn, p) : 0.0);
         if (a.temporal) {
-            double C[3], Cn[3];
-            chroma64v(Ic[0], Ic[1], Ic[2], fl, C);
-            Window3 w;
-            load_window3(a, x, y, i, w);
+            // the frame's pairs as the precompute pass found them (same gate test)
+            const unsigned gmask = (unsigned)a.tg[4 * ps + i];
+            float rp[9][3];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                chroma64v(w.I[k][0], w.I[k][1], w.I[k][2], fl, Cn);
-                if (w.ok[k] && cdist(C, Cn) < a.lam.gate) {
+                const int yy = y + k / 3 - 1, xx = x + k % 3 - 1;
+                const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+                const long long jj = ok ? (long long)yy * W + xx : i;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rp[k][c] = a.rprev[c * ps + jj];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                if ((gmask >> k) & 1u) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const double d = r[c] - (double)w.r[k][c];
+                        const double d = r[c] - (double)rp[k][c];
                         e[3] += d * d;
                     }
                 }
