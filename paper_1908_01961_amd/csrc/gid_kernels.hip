@@ -1149,13 +1149,17 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
 #pragma unroll
     for (int k = 0; k < NN; ++k) trace += Hm[k][k];
     bool ok = true;
-    // right-looking Cholesky: column j, then the trailing lower triangle
+    // right-looking Cholesky: column j, then the trailing lower triangle; lane j
+    // keeps 1 / L_jj so that the substitutions multiply instead of divide
+    double rinv = 1.0;
 #pragma unroll
     for (int j = 0; j < NN; ++j) {
         double d = rdlane(h[j], j);
         if (!(d > 1e-12 * trace)) { ok = false; d = 1.0; }
         const double ljj = sqrt(d);
-        const double lij = h[j] / ljj;
+        const double r = 1.0 / ljj;
+        const double lij = h[j] * r;
+        if (lane == j) rinv = r;
         h[j] = (lane == j) ? ljj : (lane > j ? lij : h[j]);
 #pragma unroll
         for (int k = j + 1; k < NN; ++k) {
@@ -1163,23 +1167,27 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
             if (lane >= k) h[k] -= lij * lkj;
         }
     }
-    // L y = g
+    // L y = g: lane j finishes y_j, every later lane i subtracts L_ij y_j (its own h[j])
 #pragma unroll
     for (int j = 0; j < NN; ++j) {
-        const double yj = rdlane(g, j) / rdlane(h[j], j);
+        const double yj = rdlane(g * rinv, j);
         g = (lane == j) ? yj : (lane > j ? g - h[j] * yj : g);
     }
-    // L^T x = y  (L_ji lives in lane j's h[i])
+    // L^T x = y: lane i needs column i of L (L_ji for j > i), transposed once
+    // through LDS (the Gram matrix's space, no longer needed)
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < NN; ++k)
+            if (k <= lane) Hm[lane][k] = h[k];
+    }
+    __threadfence_block();
+    double lt[NN];
+#pragma unroll
+    for (int j = 0; j < NN; ++j) lt[j] = (act && j > lane) ? Hm[j][lane] : 0.0;
 #pragma unroll
     for (int j = NN - 1; j >= 0; --j) {
-        const double xj = rdlane(g, j) / rdlane(h[j], j);
-        double lji = 0.0;
-#pragma unroll
-        for (int i = 0; i < j; ++i) {
-            const double v = rdlane(h[i], j);
-            lji = (lane == i) ? v : lji;
-        }
-        g = (lane == j) ? xj : (lane < j ? g - lji * xj : g);
+        const double xj = rdlane(g * rinv, j);
+        g = (lane == j) ? xj : (lane < j ? g - lt[j] * xj : g);
     }
     // guards: a non-positive pivot, or a colour that would leave (1e-4, inf)
     const double bold = act ? a.b64[lane] : 1.0;
