@@ -820,8 +820,10 @@ constexpr int BS_STRIDE = BS_BATCH + 1;   // padded row: rows of one pixel fall 
 template <int K>
 __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
-    constexpr int GS = (3 * K <= 32) ? 32 : 64;      // threads per pixel group
-    constexpr int NG = NTHREADS / GS;
+    // pixel groups of 3K owner threads (one per Gram row (c, k)), as many as fit a
+    // wavefront, so that few lanes idle
+    constexpr int GPW = 64 / (3 * K);                 // groups per wavefront
+    constexpr int NG = (NTHREADS / 64) * GPW;
     // per staged pixel: R_c and the data residual e_c in FP64, T_k (k >= 1) in FP32
     double* sh4 = reinterpret_cast<double*>(smem);
     double (*Rs)[BS_STRIDE] = reinterpret_cast<double (*)[BS_STRIDE]>(smem + 32);
@@ -865,8 +867,9 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
     const int lb = lc.lb;
     const int t0 = (int)(((long long)lb * a.ntiles) / lc.nb);
     const int t1 = (int)(((long long)(lb + 1) * a.ntiles) / lc.nb);
-    const int grp = threadIdx.x / GS, lane = threadIdx.x % GS;
-    const bool owner = lane < 3 * K;
+    const int wl = (int)threadIdx.x & 63, wg_in = wl / (3 * K);
+    const int grp = ((int)threadIdx.x >> 6) * GPW + wg_in, lane = wl % (3 * K);
+    const bool owner = wg_in < GPW;
     const int oc = owner ? lane / K : 0, ok = owner ? lane % K : 0;
     double acc[K + 1];
 #pragma unroll
@@ -1375,7 +1378,7 @@ constexpr size_t LDS_SMALL = 32;
 template <int K> constexpr size_t lds_gn_build() { return 32 + sizeof(float) * (K + 4) * HN; }
 template <int K> constexpr size_t lds_pcg() { return 32 * PV_N + sizeof(float) * 2 * (K + 4) * HN; }
 template <int K> constexpr size_t lds_apply_bsum() {
-    return 32 + 6 * BS_STRIDE * 8 + (NTHREADS / ((3 * K <= 32) ? 32 : 64)) * 3 * K * (K + 1) * 8 +
+    return 32 + 6 * BS_STRIDE * 8 + (NTHREADS / 64) * (64 / (3 * K)) * 3 * K * (K + 1) * 8 +
            sizeof(float) * K * BS_STRIDE;
 }
 template <int K> constexpr size_t lds_bsolve() {
