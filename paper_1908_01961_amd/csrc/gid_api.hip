@@ -575,7 +575,6 @@ static gid_status load_frame_impl(gid_ctx* c, const float* frame, const uint8_t*
     a.first = c->frame_index == 0;
     a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
     const Step s{};
-    GID_HIP(c, L1(c, c->stream, KN_RESET, a, s));
     GID_HIP(c, L1(c, c->stream, KN_SCAN, a, s));
     GID_HIP(c, L1(c, c->stream, KN_PRECOMPUTE, a, s));
     return GID_OK;
@@ -1104,7 +1103,6 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
         return hipSuccess;
     };
     const Step s0{};
-    GID_BHIP(b, each(KN_RESET, s0, st));
     GID_BHIP(b, each(KN_SCAN, s0, st));
     GID_BHIP(b, each(KN_PRECOMPUTE, s0, st));
     const gid_params& prm = b->clips[0]->prm;

@@ -126,7 +126,7 @@ struct Args {
 __host__ __device__ inline int bstep_nsums(int K) { return 3 * K * (K + 1) / 2 + 3 * K; }
 
 enum Kern : int {
-    KN_RESET = 0, KN_SCAN, KN_PRECOMPUTE, KN_GN_BUILD, KN_PCG, KN_APPLY_BSUM, KN_BSOLVE,
+    KN_SCAN = 0, KN_PRECOMPUTE, KN_GN_BUILD, KN_PCG, KN_APPLY_BSUM, KN_BSOLVE,
     KN_ENERGY, KN_ENERGY_FINISH, KN_OUTPUT, KN_TABLES, KN_CAND_TABLES, KN_JUDGE
 };
 

@@ -224,6 +224,14 @@ __device__ __forceinline__ void load3(const float* base, long long ps, long long
 // rest of the frame's kernels no-ops so the solver state is left unchanged.
 __device__ __forceinline__ void scan_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     double* sh4 = reinterpret_cast<double*>(smem);
+    // the frame's scalar bookkeeping starts from zero (no workgroup of this pass reads it)
+    if (lead_thread(lc)) {
+        a.scal[S_BREAKDOWNS] = 0.0;
+        a.scal[S_BREJECT] = 0.0;
+        a.scal[S_STOP] = 0.0;
+        a.scal[S_BADIN] = 0.0;
+        for (int g = 0; g < 64; ++g) a.scal[S_RZ_LOG + g] = 0.0;
+    }
     const long long ps = a.ps;
     double bad = 0.0;
     for_each_pixel(a, lc, [&](int x, int y, long long i) {
@@ -1362,16 +1370,6 @@ __device__ __forceinline__ void output_body(const Args& a, const Lc& lc, const S
     });
 }
 
-__device__ __forceinline__ void reset_frame_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
-    if (threadIdx.x == 0) {
-        a.scal[S_BREAKDOWNS] = 0.0;
-        a.scal[S_BREJECT] = 0.0;
-        a.scal[S_STOP] = 0.0;
-        a.scal[S_BADIN] = 0.0;
-        for (int g = 0; g < 64; ++g) a.scal[S_RZ_LOG + g] = 0.0;
-    }
-}
-
 // --------------------------------------------------------- LDS footprints
 
 constexpr size_t LDS_SMALL = 32;
@@ -1477,11 +1475,9 @@ __global__ __launch_bounds__(NTHREADS) void kb_energy_finish(const BatchArgs ba,
     extern __shared__ __align__(16) char smem[];
     energy_finish_body(ba.a[blockIdx.x], Lc{0, 1}, st, smem);
 }
-__global__ void k_reset_frame(Args a, Step st) { reset_frame_body(a, Lc{0, 1}, st, nullptr); }
 __global__ void k_tables(Args a, Step st) { tables_body(a, Lc{0, 1}, st, nullptr); }
 __global__ void k_cand_tables(Args a, Step st) { cand_tables_body(a, Lc{0, 1}, st, nullptr); }
 __global__ __launch_bounds__(NTHREADS) void k_judge(Args a, Step st) { judge_body(a, whole_grid(), st, nullptr); }
-__global__ void kb_reset_frame(const BatchArgs ba, Step st) { reset_frame_body(ba.a[blockIdx.x], Lc{0, 1}, st, nullptr); }
 
 }  // namespace
 
@@ -1508,9 +1504,6 @@ hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
     switch (k) {
         case KN_SCAN:
             hipLaunchKernelGGL(k_scan, grid, blk, LDS_SMALL, s, a, st);
-            return hipGetLastError();
-        case KN_RESET:
-            hipLaunchKernelGGL(k_reset_frame, dim3(1), dim3(64), 0, s, a, st);
             return hipGetLastError();
         case KN_ENERGY_FINISH:
             hipLaunchKernelGGL(k_energy_finish, dim3(1), blk, LDS_SMALL, s, a, st);
@@ -1554,9 +1547,6 @@ hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t 
     switch (k) {
         case KN_SCAN:
             hipLaunchKernelGGL(kb_scan, gpix, blk, LDS_SMALL, s, g.ba, st);
-            return hipGetLastError();
-        case KN_RESET:
-            hipLaunchKernelGGL(kb_reset_frame, gone, dim3(64), 0, s, g.ba, st);
             return hipGetLastError();
         case KN_ENERGY_FINISH:
             hipLaunchKernelGGL(kb_energy_finish, gone, blk, LDS_SMALL, s, g.ba, st);
