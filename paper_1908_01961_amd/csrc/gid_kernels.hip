@@ -145,9 +145,23 @@ struct PcgScalars {
     double rz, alpha, rz_next;
     bool ok;
 };
-__device__ __forceinline__ PcgScalars pcg_scalars(const Args& a, int i, int nb, double* sh4) {
+// sh: 4 doubles, or with WIDE 4 PV_N doubles (all four totals reduced behind one
+// pair of barriers; the same sums, combined in the same order)
+template <bool WIDE = false>
+__device__ __forceinline__ PcgScalars pcg_scalars(const Args& a, int i, int nb, double* sh) {
     double t[PV_N];
-    site_totals<PV_N>(a, pcg_site(i), nb, sh4, t);
+    if (WIDE) {
+        const double* p = site_ptr(a, pcg_site(i));
+#pragma unroll
+        for (int v = 0; v < PV_N; ++v) {
+            t[v] = 0.0;
+#pragma unroll
+            for (int j = 0; j < SITE_LOADS; ++j) t[v] += masked_load(p + (long long)v * nb, (int)threadIdx.x + j * NTHREADS, nb);
+        }
+        block_sums<PV_N>(t, sh);
+    } else {
+        site_totals<PV_N>(a, pcg_site(i), nb, sh, t);
+    }
     PcgScalars s;
     s.rz = t[PV_RZ];
     s.ok = t[PV_PQ] > 0.0 && isfinite(t[PV_PQ]);
@@ -579,7 +593,7 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
     double alpha = 0.0;
     float betaf = 0.0f;
     if (!first) {
-        const PcgScalars ps_ = pcg_scalars(a, it - 1, lc.nb, shr);
+        const PcgScalars ps_ = pcg_scalars<true>(a, it - 1, lc.nb, shr);
         if (!ps_.ok) {     // breakdown guard: iteration it-1 is not applied, the layer step ends
             if (lead_thread(lc)) {
                 a.scal[S_STOP] = (double)(it + 1);
