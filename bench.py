@@ -265,7 +265,8 @@ def main() -> int:
     ap.add_argument("--workload", default="video_640x480_k6")
     ap.add_argument("--frames", type=int, default=None, help="frames per clip (default: the workload's)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of graph replay")
-    ap.add_argument("--cpu-frames", type=int, default=3, help="oracle sample size in frames (0: skip)")
+    ap.add_argument("--cpu-frames", type=int, default=8,
+                    help="oracle sample size in frames, about 10 s of host work at 640x480 (0: skip)")
     ap.add_argument("--learned", choices=("on", "off"), default="on",
                     help="also compare the learned warm start with the plain method on the workload")
     ap.add_argument("--train-frames", type=int, default=2000, help="training pairs for the learned warm start")
