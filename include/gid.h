@@ -239,7 +239,9 @@ const char *gid_batch_last_error(const gid_batch *b);
 /* ---- launch-shape autotuner ----
  * Choose the number of workgroups of the per-pixel launches for this context's
  * (width, height, K) by timing the stencil kernels of a layer step on the device
- * over candidates 64..2048.  cache_path (may be NULL) is a text file of
+ * over the default (one tile per workgroup) and candidates 64..2048 up to the tile
+ * count; another shape replaces the default only when it times at least 3% faster.
+ * cache_path (may be NULL) is a text file of
  * "width height K workgroups" lines: a cached choice is reused, a new one appended.
  * Synchronous; changes no solver state other than scratch vectors. */
 gid_status gid_autotune(gid_ctx *ctx, const char *cache_path, int32_t *workgroups_out);
