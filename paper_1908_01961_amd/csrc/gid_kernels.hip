@@ -11,8 +11,8 @@
 // i % 8, and xcd_order() gives each XCD a contiguous band of tiles so that the
 // halo rows a tile shares with its vertical neighbours stay in that XCD's L2.
 //
-// Grids are persistent-style: at most a few workgroups per CU, each owning a
-// contiguous chunk of tiles (one tile each while the frame has at most 2048
+// Grids are persistent-style: at most a few workgroups per CU, each owning every
+// m-th tile of its XCD's band (one tile each while the frame has at most 2048
 // tiles), so a launch produces at most 2048 partial sums.
 // Every kernel is a body over (clip descriptor, launch context, step); a
 // single-clip launch runs it over its whole grid, a batched launch runs it for
@@ -48,6 +48,19 @@ struct Lc {
 };
 
 __device__ __forceinline__ int xcd_order(int j, int nb) { return (j & 7) * (nb >> 3) + (j >> 3); }
+
+// Tiles of a workgroup.  XCD x (workgroups x m .. x m + m - 1 in xcd_order, with
+// m = nb / 8) owns the contiguous band of tiles [x ntiles / 8, (x + 1) ntiles / 8);
+// its workgroups take the band's tiles round-robin (tile t0, t0 + m, ...), so the
+// workgroups in flight on one XCD work on neighbouring tiles and share their halo
+// lines through that XCD's L2.  With one tile per workgroup this is lb itself.
+// nb is a multiple of 8 (every per-pixel grid is).
+__device__ __forceinline__ void tiles_of(int ntiles, const Lc& lc, int& t0, int& t1, int& ts) {
+    const int m = lc.nb >> 3, x = lc.lb / m, jl = lc.lb - x * m;
+    t0 = (int)(((long long)x * ntiles) >> 3) + jl;
+    t1 = (int)(((long long)(x + 1) * ntiles) >> 3);
+    ts = m;
+}
 
 __device__ __forceinline__ Lc whole_grid() { return Lc{xcd_order((int)blockIdx.x, (int)gridDim.x), (int)gridDim.x}; }
 
@@ -170,14 +183,14 @@ __device__ __forceinline__ PcgScalars pcg_scalars(const Args& a, int i, int nb, 
     return s;
 }
 
-// Visit every pixel of this workgroup's contiguous chunk of tiles: f(x, y, i).
+// Visit every pixel of this workgroup's tiles: f(x, y, i).
 template <typename F>
 __device__ __forceinline__ void for_each_pixel(const Args& a, const Lc& lc, F&& f) {
-    const int t0 = (int)(((long long)lc.lb * a.ntiles) / lc.nb);
-    const int t1 = (int)(((long long)(lc.lb + 1) * a.ntiles) / lc.nb);
+    int t0, t1, ts;
+    tiles_of(a.ntiles, lc, t0, t1, ts);
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int rows = TYW * a.ppt;
-    for (int tile = t0; tile < t1; ++tile) {
+    for (int tile = t0; tile < t1; tile += ts) {
         const int x = (tile % a.ntx) * TX + lx;
         if (x >= a.W) continue;
         const int ybase = (tile / a.ntx) * rows + ly;
@@ -381,11 +394,6 @@ constexpr int HW = TX + 2;          // halo'd tile width
 constexpr int HH = TYW + 2;         // halo'd tile height (tiles of 64 x 4 pixels)
 constexpr int HN = HW * HH;
 
-__device__ __forceinline__ void chunk_of(const Args& a, const Lc& lc, int& t0, int& t1) {
-    t0 = (int)(((long long)lc.lb * a.ntiles) / lc.nb);
-    t1 = (int)(((long long)(lc.lb + 1) * a.ntiles) / lc.nb);
-}
-
 // IRLS weight of the reflectance-gradient term at halo'd-tile index li, from
 // the forward differences that exist (the norm over both directions and all
 // channels).  Ul holds the three r planes.
@@ -438,10 +446,10 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int li = (ly + 1) * HW + lx + 1;
     const int off[4] = {1, HW, -1, -HW};
-    int t0, t1;
-    chunk_of(a, lc, t0, t1);
+    int t0, t1, ts;
+    tiles_of(a.ntiles, lc, t0, t1, ts);
     double acc = 0.0;
-    for (int tile = t0; tile < t1; ++tile) {
+    for (int tile = t0; tile < t1; tile += ts) {
         const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TYW;
         for (int idx = threadIdx.x; idx < HN; idx += NTHREADS) {
             const int gx = x0 + idx % HW - 1, gy = y0 + idx / HW - 1;
@@ -625,12 +633,12 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
     const int ht = (int)threadIdx.x;
     const int hrow = ht < HW ? 0 : (ht < 2 * HW ? TYW + 1 : 1 + ((ht - 2 * HW) >> 1));
     const int hcol = ht < 2 * HW ? ht % HW : (((ht - 2 * HW) & 1) ? HW - 1 : 0);
-    int t0, t1;
-    chunk_of(a, lc, t0, t1);
+    int t0, t1, ts;
+    tiles_of(a.ntiles, lc, t0, t1, ts);
     double acc[PV_N];
 #pragma unroll
     for (int v = 0; v < PV_N; ++v) acc[v] = 0.0;
-    for (int tile = t0; tile < t1; ++tile) {
+    for (int tile = t0; tile < t1; tile += ts) {
         const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TYW;
         const int x = x0 + lx, y = y0 + ly;
         const bool own_in = x < W && y < H;
@@ -885,10 +893,9 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
     const bool xstored = stop0 == 0.0 ? st.iter >= 1 : stop0 >= 3.0;
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
-    // this workgroup's contiguous chunk of tiles (XCD-aware)
-    const int lb = lc.lb;
-    const int t0 = (int)(((long long)lb * a.ntiles) / lc.nb);
-    const int t1 = (int)(((long long)(lb + 1) * a.ntiles) / lc.nb);
+    // this workgroup's tiles (XCD-aware)
+    int t0, t1, ts;
+    tiles_of(a.ntiles, lc, t0, t1, ts);
     const int wl = (int)threadIdx.x & 63, wg_in = wl / (3 * K);
     const int grp = ((int)threadIdx.x >> 6) * GPW + wg_in, lane = wl % (3 * K);
     const bool owner = wg_in < GPW;
@@ -903,7 +910,7 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
         for (int c = 0; c < 3; ++c) B64[k][c] = st.refine ? a.b64[3 * k + c] : 0.0;
     const int rows = TYW * a.ppt;
     const int tile_px = TX * rows;
-    for (int tile = t0; tile < t1; ++tile) {
+    for (int tile = t0; tile < t1; tile += ts) {
         const int tx = tile % a.ntx, ty = tile / a.ntx;
         for (int base = 0; base < tile_px; base += BS_BATCH) {
             // stage: every thread owns one pixel of the batch
@@ -992,7 +999,7 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
         int idx;
         if (l < K) idx = c * (K * (K + 1) / 2) + (k * K - k * (k - 1) / 2) + (l - k);
         else       idx = 3 * K * (K + 1) / 2 + c * K + k;
-        part[(long long)idx * nb + lb] = sum;
+        part[(long long)idx * nb + lc.lb] = sum;
     }
 }
 
