@@ -174,3 +174,19 @@ def test_autotune_chooses_and_caches_a_launch_shape(torch):
         _check_first_frame(lay.cpu().numpy().astype(np.float64), b, st["energy_final"], c, "tuned launch:")
         s.close()
         s2.close()
+
+
+@pytest.mark.parametrize("nb,expect", [(8, 8), (40, 40), (2048, 64)])
+def test_few_workgroups_cover_every_tile(torch, nb, expect):
+    """Fewer workgroups than tiles: every XCD owns a band of tiles that its
+    workgroups take round-robin.  200 x 60 is 4 x 15 tiles of 64 x 4 (ragged right
+    edge), bands of 7 or 8 tiles: 8 workgroups walk a whole band each, 40 share a
+    band five ways, and a request above the tile count is clamped to it (64)."""
+    c = make_clip(200, 60, 5, 1, 406)
+    s = _solver(c)
+    s.set_workgroups(nb)
+    assert s.workgroups == expect
+    lay = torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda")
+    b, st = s.decompose_frame(_dev(torch, c.frames[0]), _dev(torch, c.ids[0]), lay)
+    _check_first_frame(lay.cpu().numpy().astype(np.float64), b, st["energy_final"], c, f"{nb} workgroups:")
+    s.close()
