@@ -3,12 +3,12 @@
  * decomposition of videos of Meka et al., "Real-Time Global Illumination
  * Decomposition of Videos".
  *
- * Problem (Sec. 3, eq. imageformation): every RGB frame I is factored as
+ * Problem (Sec. 4, eq. imageformation): every RGB frame I is factored as
  *     I(x) = R(x) * sum_{k=0..K} b_k T_k(x),   b_0 = (1,1,1),
  * into a reflectance layer R, a direct-illumination layer T_0, one indirect layer
  * T_k per base colour b_k, and K refined base colours.  The solver minimises the
- * energy of Sec. 5 (data + reflectance priors + illumination priors, l1 terms by
- * IRLS, Sec. 5.4) with the alternating scheme of Sec. 6.1: a Gauss-Newton step on
+ * energy of Sec. 6 (data + reflectance priors + illumination priors, l1 terms by
+ * IRLS, Sec. 6.4) with the alternating scheme of Sec. 7.1: a Gauss-Newton step on
  * the per-pixel layers whose normal equations get a fixed number of Jacobi-PCG
  * iterations, then a Gauss-Newton step on the base colours whose 3K x 3K normal
  * equations are summed over all pixels.
@@ -52,7 +52,7 @@ typedef enum {
     GID_ERR_UNSUPPORTED = 6
 } gid_status;
 
-/* Energy weights of Sec. 7 ("Parameters"): data 5000, clustering 200,
+/* Energy weights of Sec. 8 ("Parameters"): data 5000, clustering 200,
  * reflectance sparsity 20 with exponent p = 1, consistency 10, monochromaticity 10,
  * indirect sparsity 3, smoothness 3, non-negativity 1000, base-colour intensity
  * regulariser 10 and chromaticity regulariser 100. */
@@ -63,14 +63,15 @@ typedef struct {
 
 enum { GID_REFINE_OFF = 0, GID_REFINE_FIRST_FRAME = 1, GID_REFINE_EVERY_STEP = 2 };
 enum { GID_CR_CHROMA = 0, GID_CR_LITERAL = 1 };
+enum { GID_BSTEP_PER_PIXEL = 0, GID_BSTEP_SUM = 1 };
 
 typedef struct {
     uint32_t struct_size;      /* sizeof(gid_params), set by gid_default_params */
     int32_t K;                 /* number of base colours, 1..16 */
     gid_lambdas lambda;
-    float eps_nonneg;          /* 0.002, non-negativity reweighting (Sec. 5.4.1) */
+    float eps_nonneg;          /* 0.002, non-negativity reweighting (Sec. 6.4.1) */
     float eps_irls;            /* 0.002, guard of the l1/l_p IRLS weights */
-    float retinex_k;           /* 50, soft-Retinex weight 1 - exp(-50 dC) (Sec. 5.2) */
+    float retinex_k;           /* 50, soft-Retinex weight 1 - exp(-50 dC) (Sec. 6.2) */
     double chroma_gate;        /* 0.1, temporal pair gate on |C_t(x) - C_{t-1}(y)|_2 */
     double chroma_floor;       /* 1e-6, chromaticity is white below this intensity */
     int32_t gn_iters;          /* outer iterations per frame (G) */
@@ -80,13 +81,16 @@ typedef struct {
     int32_t cr_mode;           /* GID_CR_* */
     int32_t record_energy;     /* 1: evaluate E after every half-step (extra passes) */
     int32_t use_graph;         /* 1: replay the per-frame schedule as a hipGraph */
+    int32_t bstep_scale;       /* GID_BSTEP_*: data sum of the base-colour refinement energy
+                                  (Sec. 6.3, eq. basecolorrefinement) divided by the pixel
+                                  count (default) or the printed pixel sum */
 } gid_params;
 
 #define GID_MAX_HALF_STEPS 128
 #define GID_NUM_TERMS 8        /* data, cluster, rsparsity, rconsist, mono, isparsity, smooth, nonneg */
 
 typedef struct {
-    double energy_final;                        /* E of Sec. 5 at the frame's final state, FP64 */
+    double energy_final;                        /* E of Sec. 6 at the frame's final state, FP64 */
     double energy_terms[GID_NUM_TERMS];         /* its terms */
     double energy_half[GID_MAX_HALF_STEPS];     /* E after each half-step (record_energy) */
     double pcg_rz_last[64];                     /* <r, z> after the last PCG iteration of each GN step */
@@ -101,7 +105,7 @@ typedef struct {
     double energy_start_learned;                /* E at the network's prediction (judge), else NaN */
 } gid_frame_stats;
 
-/* Fill *out with the paper's parameters for K base colours (Sec. 7) and the
+/* Fill *out with the paper's parameters for K base colours (Sec. 8) and the
  * schedule defaults G = 3, P = 8, refinement every step, temporal prior on.
  * Errors: GID_ERR_INVALID_ARG for K outside 1..16 or out == NULL. */
 gid_status gid_default_params(int32_t K, gid_params *out);
@@ -118,13 +122,13 @@ gid_status gid_destroy(gid_ctx *ctx);
 
 /* Set the initial base-colour estimate b_k^init (K x 3 linear RGB, host memory,
  * FP64, every component > 0) and start a new clip: the next solve is a first frame
- * (Sec. 4.1 initialisation, no temporal prior).  Errors: GID_ERR_INVALID_ARG. */
+ * (Sec. 5.1 initialisation, no temporal prior).  Errors: GID_ERR_INVALID_ARG. */
 gid_status gid_set_base_colors(gid_ctx *ctx, const double *rgb_Kx3_host);
 
 /* Start a new clip with the current initial colours (as after gid_set_base_colors). */
 gid_status gid_reset_clip(gid_ctx *ctx);
 
-/* Decompose one frame (Sec. 6.1 schedule).
+/* Decompose one frame (Sec. 7.1 schedule).
  *   frame_dev       3 planes float32 (device), read during the call's stream work
  *   cluster_ids_dev width*height uint8 (device), values in [0, K)
  *   layers_dev      K+4 planes float32 (device) written: R_r, R_g, R_b, T_0..T_K; may be NULL
@@ -147,7 +151,7 @@ gid_status gid_synchronize(gid_ctx *ctx);
  * the state set by gid_set_state, so that each step can be checked on its own. */
 
 /* Load a frame without solving: per-frame precompute (chromaticity, soft-Retinex
- * weight Sec. 5.2, temporal pairs against the previous frame when params.temporal
+ * weight Sec. 6.2, temporal pairs against the previous frame when params.temporal
  * and a previous frame exists).  Initialises the state for a first frame. */
 gid_status gid_load_frame(gid_ctx *ctx, const float *frame_dev, const uint8_t *cluster_ids_dev);
 
@@ -166,7 +170,7 @@ gid_status gid_set_prev_frame(gid_ctx *ctx, const float *frame_prev_dev, const f
  * Synchronous. */
 gid_status gid_get_state(gid_ctx *ctx, float *u_dev, double *b_host);
 
-/* E of Sec. 5 and its GID_NUM_TERMS terms at the current state, FP64. Synchronous. */
+/* E of Sec. 6 and its GID_NUM_TERMS terms at the current state, FP64. Synchronous. */
 gid_status gid_eval_energy(gid_ctx *ctx, double *energy_out, double *terms_out);
 
 /* Gauss-Newton right-hand side g = -J^T F and Jacobi diagonal diag(J^T J) of the
@@ -180,7 +184,7 @@ gid_status gid_apply_normal(gid_ctx *ctx, const float *p_dev, float *q_dev);
  * may be NULL) gets the final <r, z>.  Synchronous. */
 gid_status gid_layer_step(gid_ctx *ctx, double *rz_out);
 
-/* Base-colour step sums at the current state (Sec. 6.1): A[c][k][l] =
+/* Base-colour step sums at the current state (Sec. 7.1): A[c][k][l] =
  * lam_d sum_x R_c^2 T_k T_l and h[c][k] = lam_d sum_x R_c T_k (I_c - R_c S_c),
  * FP64, host arrays of 3*K*K and 3*K doubles.  Synchronous. */
 gid_status gid_bstep_sums(gid_ctx *ctx, double *A_host, double *h_host);
@@ -194,7 +198,7 @@ gid_status gid_base_step(gid_ctx *ctx, int32_t *accepted);
  * with a HIP event pair around every launch on the context's stream; the
  * elapsed times are accumulated per kernel kind at gid_synchronize.
  * GID_KERNEL_PCG is one Jacobi-PCG iteration (vector updates fused with the
- * J^T J product, Sec. 6.1), launched pcg_iters times per layer step. */
+ * J^T J product, Sec. 7.1), launched pcg_iters times per layer step. */
 enum {
     GID_KERNEL_SCAN = 0, GID_KERNEL_PRECOMPUTE, GID_KERNEL_GN_BUILD, GID_KERNEL_PCG,
     GID_KERNEL_APPLY_BSUM, GID_KERNEL_BSOLVE, GID_KERNEL_ENERGY, GID_KERNEL_OUTPUT,
@@ -263,7 +267,7 @@ gid_status gid_load_state(gid_ctx *ctx, const void *buf, size_t bytes);
  * u_t = u_{t-1} + du) and, through a linear head on the global average of the
  * fifth layer's features, the change of the base colours db (3K).  It is this
  * project's component, not the paper's (which names learned priors only as
- * future work, Sec. 8).  The solver keeps judging it: see gid_set_warmstart.
+ * future work, Sec. 9).  The solver keeps judging it: see gid_set_warmstart.
  *
  * Parameters are one FP32 vector, in this order: for conv layer l = 0..5 its
  * weights w[o][c][dy][dx] (c_out x c_in x 3 x 3 with c_in = K + 7 for l = 0

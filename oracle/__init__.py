@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, deliberately
 unoptimised restatement of the method of "Real-Time Global Illumination
-Decomposition of Videos" (Meka et al.): the energy of Sec. 5, the IRLS
-reweighting of Sec. 5.4 and the alternating Gauss-Newton / PCG solve of Sec. 6.
+Decomposition of Videos" (Meka et al.): the energy of Sec. 6, the IRLS
+reweighting of Sec. 6.4 and the alternating Gauss-Newton / PCG solve of Sec. 7.
 It exists to check the GPU library.  Only the test-suite, the smoke check and
 the CPU-baseline leg of the benchmark may import it; the product path never
 does, and it shares no code with the HIP kernels or their binding.

@@ -1,5 +1,5 @@
 """The base-colour step (B-step): one Gauss-Newton step on the K base colours with
-the layers fixed (Sec. 5.3, eq. basecolorrefinement, and Sec. 6.1, second half).
+the layers fixed (Sec. 6.3, eq. basecolorrefinement, and Sec. 7.1, second half).
 
 Readings of eq. basecolorrefinement used here (the paper's printed form is
 ambiguous; the reasons are given in the design notes):
@@ -10,12 +10,13 @@ ambiguous; the reasons are given in the design notes):
     the distance from the initial estimate (cr_mode "chroma"); the printed
     chromaticity term reduces to |Delta b_k|^2 (cr_mode "literal");
   * the data sum of E_refine is taken per pixel (divided by the pixel count), so
-    that the two regularisers act at the scale the paper describes them for.
+    that the two regularisers act at the scale the paper describes them for
+    (bstep_scale "pixel"); bstep_scale "sum" keeps the printed pixel sum.
 The data residual I_c - R_c sum_k b_kc T_k is linear in b, so one step solves
   (A/N + lam_IR I + lam_CR sum_k J_k^T J_k) db
       = h/N - lam_IR (b - b_init) - lam_CR sum_k J_k^T (C(b_k) - C(b_k^init)),
 with A, h the per-channel data blocks summed over all N pixels (the dense part
-of the Jacobian, Sec. 6) and J_k = dC/dv at b_k.  b_0 = white is never refined.
+of the Jacobian, Sec. 7) and J_k = dC/dv at b_k.  b_0 = white is never refined.
 The paper solves this small system by SVD on the CPU; so does the oracle
 (pseudo-inverse, rcond 1e-12).  A step that would make any colour component
 fall to 1e-4 or below, or that is not finite, is rejected (db = 0).
@@ -62,11 +63,17 @@ def bstep_system(A: np.ndarray, h: np.ndarray, b: np.ndarray, b_init: np.ndarray
     N = 3 * K
     H = np.zeros((N, N))
     g = np.zeros(N)
+    if p.bstep_scale == "pixel":
+        scale = 1.0 / npix
+    elif p.bstep_scale == "sum":
+        scale = 1.0
+    else:
+        raise ValueError(p.bstep_scale)
     for c in range(3):
         for k in range(K):
-            g[3 * k + c] = h[c, k] / npix
+            g[3 * k + c] = h[c, k] * scale
             for l in range(K):
-                H[3 * k + c, 3 * l + c] += A[c, k, l] / npix
+                H[3 * k + c, 3 * l + c] += A[c, k, l] * scale
     dtot = (np.asarray(b, np.float64) - np.asarray(b_init, np.float64)).ravel()
     H += p.lam_ir * np.eye(N)
     g -= p.lam_ir * dtot
@@ -85,7 +92,7 @@ def bstep_system(A: np.ndarray, h: np.ndarray, b: np.ndarray, b_init: np.ndarray
 
 
 def bstep_solve(H: np.ndarray, g: np.ndarray, rcond: float = 1e-12) -> np.ndarray:
-    """SVD pseudo-inverse solve (Sec. 6.1 solves the small system by SVD)."""
+    """SVD pseudo-inverse solve (Sec. 7.1 solves the small system by SVD)."""
     U, s, Vt = np.linalg.svd(H)
     keep = s > rcond * s[0]
     inv = np.where(keep, 1.0 / np.where(keep, s, 1.0), 0.0)

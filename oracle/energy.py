@@ -1,9 +1,9 @@
 """Image-derived quantities and the true decomposition energy, in float64.
 
 Layout: a frame is a (3, H, W) array (planar RGB); the unknowns of one frame are a
-(K+4, H, W) array u = (r_0, r_1, r_2, T_0, T_1 .. T_K) where r = ln R (Sec. 5.1,
+(K+4, H, W) array u = (r_0, r_1, r_2, T_0, T_1 .. T_K) where r = ln R (Sec. 6.1,
 eq. clustering-term: the reflectance is optimised in the log domain) and T_0 is
-the direct and T_k the indirect illumination layers (Sec. 3, eq. imageformation).
+the direct and T_k the indirect illumination layers (Sec. 4, eq. imageformation).
 Base colours b are a (K, 3) array for k = 1..K; b_0 = (1, 1, 1) is prepended
 where the image-formation sum needs it.  Cluster ids are 0-based: id = j means
 base colour b_{j+1}.
@@ -18,18 +18,18 @@ import numpy as np
 from .params import OracleParams
 
 #: Offsets (dy, dx) of the 3x3 temporal window (reading of the spatio-temporal
-#: consistency prior of Sec. 5.1, whose sampling the paper defers to prior work).
+#: consistency prior of Sec. 6.1, whose sampling the paper defers to prior work).
 WINDOW = tuple((dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1))
 
 
 def intensity(v: np.ndarray) -> np.ndarray:
-    """|v| of Sec. 4.1 read as the channel mean (the reading under which the
-    monochrome prior of Sec. 5.2 vanishes exactly for grey illumination)."""
+    """|v| of Sec. 5.1 read as the channel mean (the reading under which the
+    monochrome prior of Sec. 6.2 vanishes exactly for grey illumination)."""
     return (v[0] + v[1] + v[2]) / 3.0
 
 
 def chromaticity(v: np.ndarray, p: OracleParams) -> np.ndarray:
-    """C = v / |v| (Sec. 4.1); white where the intensity is below the floor."""
+    """C = v / |v| (Sec. 5.1); white where the intensity is below the floor."""
     m = intensity(v)
     ok = m >= p.chroma_floor
     safe = np.where(ok, m, 1.0)
@@ -37,7 +37,7 @@ def chromaticity(v: np.ndarray, p: OracleParams) -> np.ndarray:
 
 
 def delta_chroma(C: np.ndarray) -> np.ndarray:
-    """Delta C of Sec. 5.2: the largest chromaticity difference (L2 over channels)
+    """Delta C of Sec. 6.2: the largest chromaticity difference (L2 over channels)
     to any of the four in-image neighbours."""
     _, H, W = C.shape
     out = np.zeros((H, W))
@@ -51,7 +51,7 @@ def delta_chroma(C: np.ndarray) -> np.ndarray:
 
 
 def soft_retinex_weight(I: np.ndarray, p: OracleParams) -> np.ndarray:
-    """w_SR = 1 - exp(-50 Delta C), per pixel (Sec. 5.2)."""
+    """w_SR = 1 - exp(-50 Delta C), per pixel (Sec. 6.2)."""
     return 1.0 - np.exp(-p.retinex_k * delta_chroma(chromaticity(I, p)))
 
 
@@ -76,7 +76,7 @@ def prepare_frame(I: np.ndarray, ids: np.ndarray, p: OracleParams,
                   prev_r: Optional[np.ndarray] = None) -> FrameData:
     """Per-frame fixed data: chromaticity, soft-Retinex weight and, for video,
     the temporal-consistency pairs against the previous frame's final
-    reflectance (Sec. 5.1)."""
+    reflectance (Sec. 6.1)."""
     I = np.asarray(I, np.float64)
     C = chromaticity(I, p)
     wsr = 1.0 - np.exp(-p.retinex_k * delta_chroma(C))
@@ -102,18 +102,18 @@ def prepare_frame(I: np.ndarray, ids: np.ndarray, p: OracleParams,
 
 
 def full_basis(b: np.ndarray) -> np.ndarray:
-    """(K+1, 3) basis with the white illuminant b_0 = (1,1,1) first (Sec. 3)."""
+    """(K+1, 3) basis with the white illuminant b_0 = (1,1,1) first (Sec. 4)."""
     return np.vstack([np.ones((1, 3)), np.asarray(b, np.float64)])
 
 
 def shading(T: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """S_c = sum_{k=0..K} b_{k,c} T_k (Sec. 3, eq. imageformation)."""
+    """S_c = sum_{k=0..K} b_{k,c} T_k (Sec. 4, eq. imageformation)."""
     B = full_basis(b)
     return np.einsum("kc,khw->chw", B, T)
 
 
 def cluster_log_reflectance(b: np.ndarray, ids: np.ndarray) -> np.ndarray:
-    """r_cluster = ln b_id (Sec. 4.1 and eq. clustering-term), (3, H, W)."""
+    """r_cluster = ln b_id (Sec. 5.1 and eq. clustering-term), (3, H, W)."""
     return np.log(np.asarray(b, np.float64))[ids].transpose(2, 0, 1)
 
 

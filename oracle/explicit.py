@@ -1,9 +1,9 @@
 """Row-by-row residual vector F and sparse Jacobian J of the frozen-weight
 (IRLS) least-squares problem of one layer step, and the direct Gauss-Newton
-solve J^T J delta = -J^T F (Sec. 6, the normal equations after eq. optimization).
+solve J^T J delta = -J^T F (Sec. 7, the normal equations after eq. optimization).
 
 This is an independent second statement of the residuals listed with the energy
-of Sec. 5 (one Python loop per pixel, one row per residual), used to check the
+of Sec. 6 (one Python loop per pixel, one row per residual), used to check the
 matrix-free formulas in gauss_newton.py and as the exact linear solver on small
 frames.  Column j of J is unknown j // Npx at pixel j % Npx (planar order).
 """

@@ -1,14 +1,14 @@
 """The layer step (T-step): one IRLS-reweighted Gauss-Newton step on the per-pixel
 unknowns with the base colours fixed, its normal equations solved by
-Jacobi-preconditioned conjugate gradients (Sec. 5.4 and Sec. 6.1).
+Jacobi-preconditioned conjugate gradients (Sec. 6.4 and Sec. 7.1).
 
-IRLS (Sec. 5.4): an l_p term |x|_p is replaced by |x|_2^2 * |x_old|_2^(p-2), with
+IRLS (Sec. 6.4): an l_p term |x|_p is replaced by |x|_2^2 * |x_old|_2^(p-2), with
 x_old taken at the current iterate; the weights are frozen for the whole
 Gauss-Newton step.  The l1 terms use (|x_old| + eps)^(-1); the non-negativity term
-uses 0 if T_old > 0 else (|T_old| + eps)^(-1) (Sec. 5.4.1).
+uses 0 if T_old > 0 else (|T_old| + eps)^(-1) (Sec. 6.4.1).
 
 With the weights frozen the energy is a sum of squared residuals ||F(u)||^2 and
-Gauss-Newton solves J^T J delta = -J^T F (Sec. 6, eq. optimization and the
+Gauss-Newton solves J^T J delta = -J^T F (Sec. 7, eq. optimization and the
 normal equations after it), then sets u <- u + delta.  Here J^T J and -J^T F are
 applied matrix-free, term by term; the explicit row-by-row assembly in
 explicit.py is the independent check of these formulas.
@@ -176,7 +176,7 @@ def surrogate_energy(u: np.ndarray, lin: Linearisation) -> float:
 def pcg(lin: Linearisation, iters: int, *, tol_rz: float = 0.0, g: np.ndarray | None = None,
         diag: np.ndarray | None = None):
     """Jacobi-preconditioned CG on J^T J delta = g from delta = 0, for a fixed
-    number of iterations (Sec. 6.1 uses a fixed count of data-parallel PCG steps;
+    number of iterations (Sec. 7.1 uses a fixed count of data-parallel PCG steps;
     the preconditioner and stopping rule are the readings noted in the design).
 
     Breakdown guards: stop before the update if <p, q> is not positive and

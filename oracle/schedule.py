@@ -1,4 +1,4 @@
-"""Initialisation and the alternating schedule (Sec. 6.1, sparse-dense splitting).
+"""Initialisation and the alternating schedule (Sec. 7.1, sparse-dense splitting).
 
 One frame is G outer iterations; each is a layer step (one IRLS Gauss-Newton
 step whose normal equations get P PCG iterations) followed, when refinement is
@@ -8,7 +8,7 @@ base colours; the temporal-consistency prior then ties r to the previous frame's
 final r.
 
 Initialisation of the first frame (the paper initialises R from the clustered
-reflectance, Sec. 4.1; the illumination start is a reading):
+reflectance, Sec. 5.1; the illumination start is a reading):
   r = ln b_id,  T_0 = clip(|I| / |R|, 0, 4),  T_k = 0.01 for k >= 1.
 """
 from __future__ import annotations

@@ -1,7 +1,7 @@
 """FP64 reference of the learned warm-start network (test infrastructure only).
 
 The network is not in the paper (which names learned priors only as future
-work, Sec. 8); its definition is this project's: six 3x3 convolutions with 32
+work, Sec. 9); its definition is this project's: six 3x3 convolutions with 32
 channels, ReLU after the first five, zero padding, stride 1.
 
   input   x = (I_t, u_{t-1}): 3 + n channels, n = K + 4

@@ -1,5 +1,5 @@
 // libgid host runtime: context and workspace, the per-frame schedule of the
-// alternating solve (Sec. 6.1), hipGraph replay of that schedule, single-step
+// alternating solve (Sec. 7.1), hipGraph replay of that schedule, single-step
 // access, checkpoint/resume, and the C ABI declared in gid.h.
 #include <hip/hip_runtime.h>
 
@@ -187,6 +187,7 @@ Args base_args(const gid_ctx* c) {
     a.ps = c->ps;
     a.lam = make_lam(c->prm);
     a.cr_literal = c->prm.cr_mode == GID_CR_LITERAL;
+    a.bstep_sum = c->prm.bstep_scale == GID_BSTEP_SUM;
     a.u = c->u;
     a.delta = c->delta;
     a.zA = c->zA;
@@ -376,6 +377,7 @@ gid_status check_params(const gid_params* p) {
     if (p->pcg_iters < 0 || p->pcg_iters > 4096) return GID_ERR_INVALID_ARG;
     if (p->refine_mode < 0 || p->refine_mode > 2) return GID_ERR_INVALID_ARG;
     if (p->cr_mode < 0 || p->cr_mode > 1) return GID_ERR_INVALID_ARG;
+    if (p->bstep_scale < 0 || p->bstep_scale > 1) return GID_ERR_INVALID_ARG;
     if (p->record_energy && 2 * p->gn_iters > GID_MAX_HALF_STEPS) return GID_ERR_INVALID_ARG;
     if (!(p->eps_nonneg > 0.0f) || !(p->eps_irls > 0.0f)) return GID_ERR_INVALID_ARG;
     if (!(p->lambda.p > 0.0f) || !(p->lambda.p <= 2.0f)) return GID_ERR_INVALID_ARG;
@@ -441,6 +443,7 @@ gid_status gid_default_params(int32_t K, gid_params* out) {
     p.cr_mode = GID_CR_CHROMA;
     p.record_energy = 0;
     p.use_graph = 1;
+    p.bstep_scale = GID_BSTEP_PER_PIXEL;
     *out = p;
     return GID_OK;
 }

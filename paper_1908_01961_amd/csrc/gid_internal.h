@@ -79,6 +79,7 @@ struct Args {
     int temporal;            // consistency prior active for this frame
     int first;               // initialise the unknowns (first frame of a clip)
     int cr_literal;
+    int bstep_sum;           // base-colour data sum not divided by the pixel count
     float* u;                // n planes
     float* delta;            // x: the layer step accumulated by PCG
     float* zA;               // preconditioned residual z = M^-1 r, even PCG iterations from 2

@@ -1120,7 +1120,7 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
         for (int e = threadIdx.x; e < NS; e += blockDim.x) a.bsum[e] = sums[e];
         return;
     }
-    const double npix = (double)a.W * (double)a.H;
+    const double npix = a.bstep_sum ? 1.0 : (double)a.W * (double)a.H;
     const double lir = a.lam.ir, lcr = a.lam.cr;
     for (int e = threadIdx.x; e < NN * NN; e += blockDim.x) {
         const int row = e / NN, col = e % NN;

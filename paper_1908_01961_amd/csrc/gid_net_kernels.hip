@@ -2,7 +2,7 @@
 // (32 channels, ReLU, BF16 weights and activations, FP32 accumulation) that
 // predicts the change of the unknowns and of the base colours from one frame to
 // the next.  The network is this project's own component; the paper names
-// learned priors only as future work (Sec. 8).
+// learned priors only as future work (Sec. 9).
 //
 // Every convolution is an implicit GEMM on the gfx950 matrix cores
 // (v_mfma_f32_16x16x32_bf16): M = 16 pixels, N = 16 output channels, and the

@@ -20,6 +20,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime er
           4: "non-finite value", 5: "call out of order", 6: "unsupported"}
 REFINE = {"off": 0, "first": 1, "every": 2}
 CR = {"chroma": 0, "literal": 1}
+BSTEP = {"pixel": 0, "sum": 1}
 KERNEL_KINDS = ("scan", "precompute", "gn_build", "pcg", "apply_bsum", "bsolve", "energy",
                 "output")
 TERMS = ("data", "cluster", "rsparsity", "rconsist", "mono", "isparsity", "smooth", "nonneg")
@@ -37,7 +38,7 @@ class GidParams(ctypes.Structure):
                 ("chroma_gate", c_double), ("chroma_floor", c_double),
                 ("gn_iters", c_int32), ("pcg_iters", c_int32), ("refine_mode", c_int32),
                 ("temporal", c_int32), ("cr_mode", c_int32), ("record_energy", c_int32),
-                ("use_graph", c_int32)]
+                ("use_graph", c_int32), ("bstep_scale", c_int32)]
 
 
 class GidFrameStats(ctypes.Structure):
@@ -145,6 +146,8 @@ def default_params(K: int, **overrides) -> GidParams:
             v = REFINE[v]
         if k == "cr_mode" and isinstance(v, str):
             v = CR[v]
+        if k == "bstep_scale" and isinstance(v, str):
+            v = BSTEP[v]
         if k.startswith("lam_"):
             setattr(p.lambda_, k[4:], v)
         else:

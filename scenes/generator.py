@@ -3,7 +3,7 @@
 This module only *renders inputs*: it draws a scene (base colours, a Voronoi
 reflectance map, a smooth direct-shading field and one Gaussian indirect blob per
 base colour) and renders frames with the paper's image-formation model
-(Sec. 3, eq. imageformation: I = R * sum_k b_k T_k with b_0 = white) plus i.i.d.
+(Sec. 4, eq. imageformation: I = R * sum_k b_k T_k with b_0 = white) plus i.i.d.
 Gaussian noise.  It holds none of the solver's arithmetic (no energy, weights,
 Jacobians or solves); both the FP64 oracle and the GPU library consume the
 arrays it returns.

@@ -4,7 +4,7 @@ The bar: layers within 1e-3 absolute, final energy within 1e-4 relative, base
 colours within 1e-3.
 
 One part of the method is discontinuous: the non-negativity reweighting of an
-indirect layer (Sec. 5.4.1) gives a zero weight where T > 0 and a weight up to
+indirect layer (Sec. 6.4.1) gives a zero weight where T > 0 and a weight up to
 lambda / eps = 5e5 where T <= 0, and that weight pins most indirect-layer
 values within 1e-4 of zero (at the start of the last step of the 640x480
 first frame, 37% of the pixels have some |T_k| < 1e-4 and 0.04% some

@@ -346,6 +346,22 @@ def test_refine_modes_and_literal_cr(torch):
     _anchored(torch, c, 2, 8, 3, cr_mode="literal")
 
 
+def test_printed_pixel_sum_bstep_scale(torch):
+    """The base-colour data sum taken as printed (bstep_scale "sum", Sec. 6.3):
+    on the 64x48 K = 4 scene every base-colour step of a 3 x 10 schedule would
+    drive a colour component below 1e-4 and is rejected, on both sides."""
+    _say("bstep_scale=sum, single_64x48_k4 3x10")
+    c = workload_clip("single_64x48_k4")
+    ps = O.default_params(bstep_scale="sum", state_precision="f32")
+    gpu = _run_gpu_clip(torch, c, 3, 10, 1, False, bstep_scale="sum")
+    orc = _oracle_clip(c, 3, 10, temporal=False, p=ps)
+    assert all(e_b == e_t for (_, e_t), (_, e_b) in zip(orc[0].energies[0::2], orc[0].energies[1::2]))
+    assert gpu[0]["stats"]["bstep_rejected"] == 3
+    assert np.array_equal(gpu[0]["b"], c.b_init)
+    rep = _compare(gpu, orc, 10, "bstep_scale=sum")
+    assert rep[0]["n_over"] == 0
+
+
 # --------------------------------------------------- determinism, graph, resume
 
 def test_graph_replay_matches_direct_launches_bitwise(torch):

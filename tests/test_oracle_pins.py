@@ -355,7 +355,7 @@ def test_single_region_exact_recovery():
 
 
 def test_sparsity_prior_confines_indirect_layers():
-    """Sec. 8 sparsity-prior ablation: without the indirect-sparsity prior more
+    """Sec. 8.2 (evaluation of the sparsity prior) ablation: without the indirect-sparsity prior more
     pixels carry indirect light."""
     c = workload_clip("single_64x48_k4")
     def active(lam):
