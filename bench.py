@@ -1,18 +1,34 @@
 #!/usr/bin/env python3
-"""Decomposed Mpixel/s of the alternating Gauss-Newton decomposition on one MI355X.
+"""Decomposed Mpixel/s at a fixed final energy on one MI355X: the learned warm
+start against the plain method.
 
-A step decomposes one whole synthetic clip: every frame goes through the fixed
-schedule (G outer iterations of a layer step with P PCG iterations and a
-base-colour step), warm-started from the previous frame with the temporal
-prior on, starting from the initial colour estimate.  Inputs are resident in
-device memory before timing starts; per-frame layers are written to device
-memory.  Default workload: 640x480, 30 frames, K = 6, G x P = 3 x 8.
+Default workload: 1920x1080, 120 frames, K = 10, the plain schedule G x P = 3 x 8
+(Sec. 7.1: G outer iterations of a layer step with P PCG iterations and a
+base-colour step), temporal prior on.  Frame 0 (which has no previous frame to
+warm-start from) is solved once with the plain schedule and checkpointed; a
+step then decomposes frames 1..F-1 from that checkpoint.
 
-Prints one JSON line.  Besides the throughput it reports the roofline of the
-dominant kernel (the PCG iteration: vector updates fused with the matrix-free
-J^T J product, timed with HIP events on the solver's stream in a profiled pass
-over the same clip) and the FP64 oracle
-timed on host cores on a bounded sample of the same workload.
+  plain    every frame warm-started from the previous result, fixed 3 x 8.
+  learned  the network's prediction from the previous result, judged against
+           it by the energy, then outer iterations until the frame's energy is
+           at or below the plain method's final energy on that frame times
+           (1 + 1e-4), up to 2 G iterations (device-side stop, no host trips).
+           Network inference, the judge and every energy evaluation are timed.
+
+The learned run counts as matched when every frame meets its target.  `value`
+is the throughput at the fixed final energy: the learned path's when matched
+and faster, else the plain path's (config.method says which); both are
+reported, with the speed-up.  Inputs are resident in device memory before
+timing starts.
+
+Also reported: the roofline of the dominant kernel (the PCG iteration, vector
+updates fused with the matrix-free J^T J product; HIP events on the solver's
+stream in a profiled pass) against the algorithmic bytes per pixel of the
+method, (7n + 1 + tau) * 4 per PCG iteration, and per frame
+4 G [P (7n + 1 + tau) + 7n + 7 + 3 tau]; the FP64 oracle timed on the host on a
+bounded sample (one full-size frame) and on the 96 x 54 area-averaged copy of
+the clip; plain-method lines for 640x480 and 1280x720; and the batch of 16
+uneven clips (shared launches against one clip after another).
 """
 from __future__ import annotations
 
@@ -27,23 +43,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "decomposed Mpixel/s at fixed final energy (1 GPU); learned warm-start vs plain"
+GEN_WORKERS = 16
 
 
-def algorithmic_bytes(n: int, tau: int, G: int, P: int) -> dict:
-    """Bytes per pixel the method must move with FP32 state and the operator
-    recomputed from the unknowns; the PCG vectors are carried in preconditioned
-    form (z = M^-1 r and M^-1 q).  A PCG iteration i > 1 reads u, z, M^-1 q, p, x
-    and M^-1 (n planes each), the soft-Retinex weight and the temporal pair count,
-    and writes x, z, p and M^-1 q; iteration 1 starts x from zero and reads p0 = z0
-    once; the first iteration reads u, p0 and M^-1 and writes M^-1 q.  The build
-    reads u, the frame, the weight and the temporal sums and writes M^-1 and p0;
-    the apply reads u, x and p and writes u."""
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def method_bytes(n: int, tau: int, G: int, P: int) -> dict:
+    """Algorithmic bytes per pixel of the method (FP32 state, operator recomputed
+    from the unknowns, q kept on chip): a PCG iteration reads u, the per-pixel
+    data and the state and reads and writes x, r and p, (7n + 1 + tau) * 4; the
+    build (3n + 4 + 3 tau) * 4, the apply 3n * 4, the base-colour sums (n + 3) * 4."""
+    it = 7 * n + 1 + tau
+    return dict(pcg=4 * it, frame=4 * G * (P * it + 7 * n + 7 + 3 * tau))
+
+
+def impl_bytes(n: int, tau: int, P: int) -> float:
+    """Bytes per pixel the implementation's PCG launches move on average: with
+    the vectors carried in preconditioned form an iteration i > 1 reads u, z,
+    M^-1 q, p, x and M^-1 (n planes each), the soft-Retinex weight and the
+    temporal pair count, and writes x, z, p and M^-1 q; iteration 1 starts x
+    from zero; iteration 0 reads u, p0 and M^-1 and writes M^-1 q."""
     its = [4 * n + 1 + tau, 8 * n + 1 + tau] + [10 * n + 1 + tau] * max(0, P - 2)
-    pcg_total = sum(its[:P])
-    build = 3 * n + 4 + 4 * tau
-    apply = 4 * n + 3
-    return dict(pcg=4 * pcg_total / max(P, 1),            # average per PCG launch
-                frame=4 * G * (pcg_total + build + apply))
+    return 4.0 * sum(its[:P]) / max(P, 1)
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -65,7 +89,9 @@ def measured_traffic(kernel: str, workload: str):
     return int(m.group(2))
 
 
-def cpu_baseline(clip, G, P, frames):
+def oracle_rate(clip, G, P, frames, what):
+    """The FP64 oracle (test infrastructure, timed here only as the CPU baseline)
+    on the first `frames` frames of a clip, one host thread."""
     from threadpoolctl import threadpool_limits
     import oracle as O
     with threadpool_limits(1):
@@ -75,131 +101,172 @@ def cpu_baseline(clip, G, P, frames):
         dt = time.perf_counter() - t0
     px = frames * clip.width * clip.height
     return dict(value=px / dt / 1e6, unit="Mpx/s", cores=1, kind="oracle",
-                sample=f"first {frames} frame(s) of the {clip.width}x{clip.height} K={clip.K} clip, "
-                       f"same {G}x{P} schedule, FP64 NumPy, 1 thread; {dt:.1f} s",
+                sample=f"{what}: first {frames} frame(s) of {clip.width}x{clip.height} K={clip.K}, same "
+                       f"{G}x{P} schedule, FP64 NumPy, 1 thread; {dt:.1f} s",
                 host_cpus=os.cpu_count(), host_affinity=len(os.sched_getaffinity(0)))
 
 
-def learned_vs_plain(clip, w, train_frames: int, log):
-    """The learned warm start against the plain method on the same clip.
+class Video:
+    """A clip resident on the device with a frame-0 checkpoint of the plain schedule."""
 
-    Frame 0 (no previous frame to warm-start from) runs the plain schedule and
-    is checkpointed; every candidate then solves frames 1..F-1 from that
-    checkpoint.  The network is trained first (untimed) on train_frames pairs
-    from plain decompositions of synthetic clips with seeds disjoint from the
-    workload's.  A schedule counts as matched when on every frame its final
-    energy is at most the plain method's times (1 + 1e-4).  Timed passes run
-    the frames back to back on the device; energies come from a separate pass
-    with per-frame statistics."""
-    import numpy as np
-    import torch
+    def __init__(self, clip, G_, P_):
+        import torch
+        import paper_1908_01961_amd as G
+        self.clip, self.G, self.P = clip, G_, P_
+        self.K, self.W, self.H, self.F = clip.K, clip.width, clip.height, clip.nframes
+        self.frames = torch.from_numpy(clip.frames).cuda()
+        self.ids = torch.from_numpy(clip.ids).cuda()
+        self.layers = torch.empty((self.K + 4, self.H, self.W), dtype=torch.float32, device="cuda")
+        s = self.solver()
+        s.set_base_colors(clip.b_init)
+        s.decompose_frame(self.frames[0], self.ids[0], self.layers)
+        self.blob = s.save_state()
+        s.close()
+        self.px = (self.F - 1) * self.W * self.H
 
+    def solver(self, G_=None):
+        import paper_1908_01961_amd as G
+        return G.Solver(self.W, self.H, G.default_params(self.K, gn_iters=G_ or self.G, pcg_iters=self.P,
+                                                         temporal=1, refine_mode="every", record_energy=0,
+                                                         use_graph=1))
+
+    def pass_(self, s, targets=None, max_gn=0):
+        """Frames 1..F-1 from the checkpoint; per-frame (energy, outer iterations)."""
+        s.load_state(self.blob)
+        out = []
+        for t in range(1, self.F):
+            if targets is not None:
+                s.set_energy_target(targets[t - 1], max_gn)
+            _, st = s.decompose_frame(self.frames[t], self.ids[t], self.layers)
+            out.append((st["energy_final"], st["gn_done"], st["warm_start_learned"]))
+        return out
+
+    def timed(self, s, steps, warmup, targets=None, max_gn=0):
+        import torch
+        for _ in range(warmup):
+            self.pass_(s, targets, max_gn)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = None
+        for _ in range(steps):
+            last = self.pass_(s, targets, max_gn)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, last
+
+
+def kernel_roofline(video, s, workload):
+    """Profiled pass (direct launches, HIP events around every launch on the
+    solver's stream): the PCG iteration's average duration against the method's
+    bytes, and each kernel's share."""
+    s.set_profiling(True)
+    video.pass_(s)
+    kt = s.kernel_times()
+    s.set_profiling(False)
+    n, tau = video.K + 4, 1
+    mv = kt["pcg"]
+    avg_s = mv["ms"] / max(1, mv["launches"]) / 1e3
+    npx = video.W * video.H
+    mb = method_bytes(n, tau, video.G, video.P)["pcg"] * npx
+    ib = impl_bytes(n, tau, video.P) * npx
+    rf = dict(bound="hbm", kernel="k_pcg", achieved=round(mb / avg_s / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+              frac=round(mb / avg_s / 1e9 / HBM_PEAK_GBS, 4), traffic=measured_traffic("k_pcg", workload),
+              algorithmic_bytes_per_launch=mb, algorithmic_bytes_per_pixel=method_bytes(n, tau, video.G, video.P)["pcg"],
+              avg_launch_us=round(avg_s * 1e6, 2),
+              implementation_bytes_per_launch=round(ib), implementation_gbs=round(ib / avg_s / 1e9, 1))
+    kernels = {k: dict(avg_us=round(v["ms"] * 1e3 / v["launches"], 2), launches=v["launches"],
+                       share=round(v["ms"] / max(1e-12, sum(x["ms"] for x in kt.values())), 4))
+               for k, v in kt.items() if v["launches"]}
+    return rf, kernels
+
+
+def frame_roofline(video, sec_per_frame):
+    mb = method_bytes(video.K + 4, 1, video.G, video.P)["frame"] * video.W * video.H
+    gbs = mb / sec_per_frame / 1e9
+    return dict(achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(gbs / HBM_PEAK_GBS, 4),
+                algorithmic_bytes_per_frame=mb)
+
+
+def train_network(video, train_frames):
     import paper_1908_01961_amd as G
     from paper_1908_01961_amd import warmstart as WSP
-
-    W_, H_, K, F = clip.width, clip.height, clip.K, clip.nframes
-    Gp, Pp = w["G"], w["P"]
-    frames = torch.from_numpy(clip.frames).cuda()
-    ids = torch.from_numpy(clip.ids).cuda()
-
-    def ctx(g, p):
-        return G.Solver(W_, H_, G.default_params(K, gn_iters=g, pcg_iters=p, temporal=1, refine_mode="every",
-                                                 record_energy=0, use_graph=1))
-
-    s0 = ctx(Gp, Pp)
-    s0.set_base_colors(clip.b_init)
-    s0.decompose_frame(frames[0], ids[0])
-    blob = s0.save_state()
-    s0.close()
-
-    def run(g, p, net=None):
-        s = ctx(g, p)
-        s.load_state(blob)
-        if net is not None:
-            s.set_warmstart(net)
-        E, taken = [], 0
-        for t in range(1, F):
-            _, st = s.decompose_frame(frames[t], ids[t])
-            E.append(st["energy_final"])
-            taken += st["warm_start_learned"] == 1
-        best = None
-        for _ in range(3):
-            s.load_state(blob)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for t in range(1, F):
-                s.decompose_frame_async(frames[t], ids[t])
-            s.synchronize()
-            dt = time.perf_counter() - t0
-            best = dt if best is None else min(best, dt)
-        s.close()
-        return np.array(E), best, taken
-
-    px = (F - 1) * W_ * H_
-    E_plain, t_plain, _ = run(Gp, Pp)
-    log(f"plain {Gp}x{Pp}: {px / t_plain / 1e6:.1f} Mpx/s on frames 1..{F - 1}")
+    W_, H_, K = video.W, video.H, video.K
     t0 = time.perf_counter()
     f = 2
     while (W_ // f) * (H_ // f) > 80000:
         f += 1
-    tw, th = max(64, W_ // f), max(32, H_ // f)       # training frames: the workload's aspect, ~77k pixels
-    store = WSP.make_training_set(K, tw, th, train_frames, 41, Gp, Pp, 10000)
+    tw, th = max(64, W_ // f), max(32, H_ // f)       # the workload's aspect, about 77k pixels
+    store = WSP.make_training_set(K, tw, th, train_frames, 41, video.G, video.P, 10000)
     net_t = G.Net(K, tw, th)
     net_t.set_params(WSP.init_params(K, 1))
     hist = WSP.train(net_t, store, epochs=4, lr=1e-3)
     del store
     net = WSP.transfer(net_t, K, W_, H_)
     net_t.close()
-    train_s = time.perf_counter() - t0
-    log(f"network trained on {train_frames} pairs at {tw}x{th} in {train_s:.1f} s (loss {hist[-1]:.3e})")
+    secs = time.perf_counter() - t0
+    log(f"network trained on {train_frames} pairs at {tw}x{th} in {secs:.1f} s (loss {hist[-1]:.3e})")
+    return net, dict(pairs=train_frames, size=f"{tw}x{th}", seconds=round(secs, 1), final_loss=hist[-1],
+                     seeds="10000 and up")
 
-    def summary(E, dt, taken=None):
-        ex = E / E_plain - 1.0
-        d = dict(mpx_s=round(px / dt / 1e6, 2), frames_s=round((F - 1) / dt, 1),
-                 energy_excess_max=float(ex.max()), energy_excess_median=float(np.median(ex)),
-                 matched=bool(ex.max() <= 1e-4))
-        if taken is not None:
-            d["learned_start_taken"] = f"{taken}/{F - 1}"
-        return d
 
-    scheds = []
-    for g, p in ((1, Pp), (2, Pp), (Gp, Pp)):
-        E_l, t_l, taken = run(g, p, net)
-        row = dict(schedule=f"{g}x{p}", learned=summary(E_l, t_l, taken))
-        if (g, p) != (Gp, Pp):
-            E_r, t_r, _ = run(g, p)
-            row["plain_same_schedule"] = summary(E_r, t_r)
-        scheds.append(row)
-        log(f"learned {g}x{p}: {row['learned']}")
+def bench_video(args, clip, workload, learned=True):
+    import numpy as np
+    from scenes import WORKLOADS
+    w = WORKLOADS[workload]
+    video = Video(clip, w["G"], w["P"])
+    s = video.solver()
+    plain = video.pass_(s)
+    E_plain = np.array([e for e, _, _ in plain])
+    t_plain, _ = video.timed(s, args.steps, args.warmup)
+    plain_mpx = video.px / t_plain / 1e6
+    log(f"{workload} plain {w['G']}x{w['P']}: {t_plain * 1e3:.1f} ms per pass of {video.F - 1} frames, "
+        f"{plain_mpx:.1f} Mpx/s")
+    rf, kernels = kernel_roofline(video, s, workload)
+    s.close()
+    res = dict(video=video, t_plain=t_plain, plain_mpx=plain_mpx, roofline=rf, kernels=kernels,
+               frame_roofline=frame_roofline(video, t_plain / (video.F - 1)), E_plain=E_plain)
+    if not learned:
+        return res
+    net, train = train_network(video, args.train_frames)
+    max_gn = 2 * w["G"]
+    targets = E_plain * (1.0 + 1e-4)
+    sl = video.solver(max_gn)
+    sl.set_warmstart(net)
+    t_l, last = video.timed(sl, args.steps, args.warmup, targets, max_gn)
+    E_l = np.array([e for e, _, _ in last])
+    gn = np.array([g for _, g, _ in last])
+    taken = int(sum(1 for _, _, k in last if k == 1))
+    sl.close()
     net.close()
-    plain_mpx = px / t_plain / 1e6
-    matched = [r for r in scheds if r["learned"]["matched"]]
-    best = max(matched, key=lambda r: r["learned"]["mpx_s"]) if matched else None
-    return dict(frames_timed=F - 1, plain=dict(schedule=f"{Gp}x{Pp}", mpx_s=round(plain_mpx, 2)),
-                train=dict(pairs=train_frames, size=f"{tw}x{th}", seconds=round(train_s, 1), final_loss=hist[-1],
-                           seeds="10000 and up"),
-                schedules=scheds,
-                criterion="E_learned[t] <= E_plain[t] * (1 + 1e-4) for every frame t >= 1",
-                best_matched_schedule=best["schedule"] if best else None,
-                speedup_at_matched_energy=round(best["learned"]["mpx_s"] / plain_mpx, 3) if best else None)
+    matched = bool(np.all(E_l <= targets))
+    l_mpx = video.px / t_l / 1e6
+    ex = E_l / E_plain - 1.0
+    log(f"learned + continuation: {t_l * 1e3:.1f} ms per pass, {l_mpx:.1f} Mpx/s, outer iterations "
+        f"mean {gn.mean():.2f} (max {gn.max()}), matched {matched}")
+    res["learned"] = dict(
+        frames_timed=video.F - 1, criterion="E_learned[t] <= E_plain[t] * (1 + 1e-4) for every frame t >= 1",
+        plain=dict(schedule=f"{w['G']}x{w['P']}", mpx_s=round(plain_mpx, 2),
+                   frames_s=round((video.F - 1) / t_plain, 1)),
+        learned=dict(mpx_s=round(l_mpx, 2), frames_s=round((video.F - 1) / t_l, 1), max_gn=max_gn,
+                     gn_mean=round(float(gn.mean()), 3), gn_max=int(gn.max()),
+                     gn_histogram={int(g): int((gn == g).sum()) for g in np.unique(gn)},
+                     learned_start_taken=f"{taken}/{video.F - 1}",
+                     energy_excess_max=float(ex.max()), energy_excess_median=float(np.median(ex)),
+                     matched=matched),
+        train=train,
+        speedup_at_matched_energy=round(t_plain / t_l, 3) if matched else None)
+    res["t_learned"] = t_l
+    return res
 
 
-def bench_batch(args, log):
+def bench_batch(args, clips):
     """Sixteen clips of mixed size (320x240 ... 1280x720), length (8-32 frames) and K
     (4-8), all advanced one frame per call through shared launches (gid_batch_*),
     against the same contexts solving the clips one after another.  Each clip's
-    launch shape comes from the autotuner (untimed).  A step is one pass over
-    every frame of every clip, from the initial colours."""
+    launch shape comes from the autotuner (untimed).  A pass covers every frame of
+    every clip, from the initial colours."""
     import tempfile
-
     import torch
-
     import paper_1908_01961_amd as G
-    from scenes import make_clip, mixed_batch_specs
-
-    specs = mixed_batch_specs(16, 400)
-    clips = [make_clip(sp["width"], sp["height"], sp["K"], sp["frames"], sp["seed"]) for sp in specs]
-    log(f"{len(clips)} clips generated")
     solvers = [G.Solver(c.width, c.height, G.default_params(c.K, gn_iters=3, pcg_iters=8, temporal=1,
                                                             record_energy=0, use_graph=1)) for c in clips]
     with tempfile.TemporaryDirectory() as d:
@@ -223,38 +290,28 @@ def bench_batch(args, log):
             s.set_base_colors(c.b_init)
             for t in range(c.nframes):
                 s.decompose_frame_async(frames[i][t], ids[i][t])
-            s.synchronize()
+                s.synchronize()
 
-    def timed(fn):
-        for _ in range(args.warmup):
-            fn()
+    def timed(fn, steps):
+        fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             fn()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / args.steps
+        return (time.perf_counter() - t0) / steps
 
-    t_b = timed(step_batch)
-    log(f"batched: {t_b * 1e3:.1f} ms per pass, {px / t_b / 1e6:.1f} Mpx/s")
-    t_s = timed(step_sequential)
-    log(f"one clip after another: {t_s * 1e3:.1f} ms per pass, {px / t_s / 1e6:.1f} Mpx/s")
+    steps = max(1, min(args.steps, 3))
+    t_b = timed(step_batch, steps)
+    t_s = timed(step_sequential, steps)
+    log(f"batch of {len(clips)}: batched {px / t_b / 1e6:.1f} Mpx/s, one after another {px / t_s / 1e6:.1f} Mpx/s")
     batch.close()
     for s in solvers:
         s.close()
-    out = {
-        "metric": "decomposed Mpixel/s at fixed final energy (1 GPU); learned warm-start vs plain",
-        "value": round(px / t_b / 1e6, 2), "unit": "Mpx/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(t_b * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 (f64 reductions)", "data": "synthetic",
-        "config": {"workload": "batch_16_mixed", "clips": [dict(width=c.width, height=c.height, frames=c.nframes,
-                                                                K=c.K, workgroups=n) for c, n in zip(clips, shapes)],
-                   "pixels_per_step": px, "gn_iters": 3, "pcg_iters": 8, "temporal": True, "method": "plain"},
-        "sequential": {"mpx_s": round(px / t_s / 1e6, 2), "ms_per_step": round(t_s * 1e3, 3)},
-        "batched_over_sequential": round(t_s / t_b, 3),
-    }
-    print(json.dumps(out), flush=True)
-    return 0
+    return dict(mpx_s=round(px / t_b / 1e6, 2), ms_per_pass=round(t_b * 1e3, 2),
+                sequential_mpx_s=round(px / t_s / 1e6, 2), batched_over_sequential=round(t_s / t_b, 3),
+                pixels_per_pass=px, clips=[dict(width=c.width, height=c.height, frames=c.nframes, K=c.K,
+                                                workgroups=n) for c, n in zip(clips, shapes)])
 
 
 def main() -> int:
@@ -262,139 +319,103 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="video_640x480_k6")
+    ap.add_argument("--workload", default="video_1920x1080_k10")
     ap.add_argument("--frames", type=int, default=None, help="frames per clip (default: the workload's)")
-    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly instead of graph replay")
-    ap.add_argument("--cpu-frames", type=int, default=8,
-                    help="oracle sample size in frames, about 10 s of host work at 640x480 (0: skip)")
-    ap.add_argument("--learned", choices=("on", "off"), default="on",
-                    help="also compare the learned warm start with the plain method on the workload")
+    ap.add_argument("--learned", choices=("on", "off"), default="on")
     ap.add_argument("--train-frames", type=int, default=2000, help="training pairs for the learned warm start")
+    ap.add_argument("--extras", choices=("on", "off"), default="on",
+                    help="also the 640x480 and 1280x720 plain lines and the 16-clip batch")
+    ap.add_argument("--cpu", choices=("on", "off"), default="on", help="time the FP64 oracle on the host")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device 5 times: a plain copy "
                          "of known size for scaling hardware byte counters (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the solver is single-GPU (clips would shard across GPUs with "
-              "no communication); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the solver runs on one GPU (independent clips would shard across "
+              "GPUs with no communication); run with --gpus 1", file=sys.stderr)
         return 2
 
-    import numpy as np
-    import torch
-
-    import paper_1908_01961_amd as G
-    from scenes import WORKLOADS, workload_clip
-
-    if args.workload == "batch_16_mixed":
-        return bench_batch(args, lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    # inputs are rendered on the host before anything touches the GPU (the renderer forks)
+    from scenes import WORKLOADS, downsample_clip, make_clip, mixed_batch_specs, workload_clip
     w = WORKLOADS[args.workload]
     F = args.frames or w["frames"]
-    print(f"[bench] generating {args.workload} ({F} frames)", file=sys.stderr, flush=True)
-    clip = workload_clip(args.workload, nframes=F)
-    W_, H_, K = clip.width, clip.height, clip.K
-    n = K + 4
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    frames = torch.from_numpy(clip.frames).to(dev)
-    ids = torch.from_numpy(clip.ids).to(dev)
-    layers = torch.empty((F, n, H_, W_), dtype=torch.float32, device=dev)
-    prm = G.default_params(K, gn_iters=w["G"], pcg_iters=w["P"], temporal=int(w["temporal"]),
-                           refine_mode="every", record_energy=0, use_graph=0 if args.no_graph else 1)
-    solver = G.Solver(W_, H_, prm)
-
-    def step():
-        solver.set_base_colors(clip.b_init)
-        for t in range(F):
-            solver.decompose_frame_async(frames[t], ids[t], layers[t])
-        return solver.synchronize()
-
-    for i in range(args.warmup):
-        step()
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record()
-    last = None
-    for _ in range(args.steps):
-        last = step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = wall * 1e3 / args.steps
-    px = F * W_ * H_
-    value = px * args.steps / wall / 1e6
-    print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} Mpx/s", file=sys.stderr,
-          flush=True)
-    b_final, stats = last
+    clip = workload_clip(args.workload, nframes=F, gt=False, workers=GEN_WORKERS)
+    log(f"generated {args.workload} ({F} frames) in {time.perf_counter() - t0:.1f} s")
+    extra_clips = {}
+    if args.extras == "on":
+        for name in ("video_640x480_k6", "video_1280x720_k8"):
+            if name != args.workload:
+                extra_clips[name] = workload_clip(name, gt=False, workers=GEN_WORKERS)
+        specs = mixed_batch_specs(16, 400)
+        extra_clips["batch_16_mixed"] = [make_clip(sp["width"], sp["height"], sp["K"], sp["frames"], sp["seed"],
+                                                   gt=False, workers=GEN_WORKERS) for sp in specs]
+        log("generated the extra workloads")
 
-    # profiled pass: per-kernel durations from HIP events on the solver's stream
-    solver.set_profiling(True)
-    step()
-    kt = solver.kernel_times()
-    solver.set_profiling(False)
-    mv = kt["pcg"]
-    mv_avg_s = mv["ms"] / max(1, mv["launches"]) / 1e3
-    tau = 1 if w["temporal"] else 0
-    ab = algorithmic_bytes(n, tau, w["G"], w["P"])
-    mv_bytes = ab["pcg"] * W_ * H_
-    achieved = mv_bytes / mv_avg_s / 1e9
-    frame_ms = ms_per_step / F
-    frame_gbs = ab["frame"] * W_ * H_ / (frame_ms / 1e3) / 1e9
-    roofline = dict(bound="hbm", kernel="k_pcg", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic("k_pcg", args.workload),
-                    algorithmic_bytes_per_launch=mv_bytes, avg_launch_us=round(mv_avg_s * 1e6, 2))
-    kernels = {k: dict(avg_us=round(v["ms"] * 1e3 / v["launches"], 2), launches=v["launches"],
-                       share=round(v["ms"] / max(1e-12, sum(x["ms"] for x in kt.values())), 4))
-               for k, v in kt.items() if v["launches"]}
+    import torch
+    torch.cuda.set_device(0)
+    import paper_1908_01961_amd as G
+    G.load_library()
 
-    learned = None
-    if args.learned == "on":
-        learned = learned_vs_plain(clip, w, args.train_frames,
-                                   lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    main_res = bench_video(args, clip, args.workload, learned=args.learned == "on")
+    video = main_res["video"]
+    lv = main_res.get("learned")
+    use_learned = bool(lv and lv["learned"]["matched"] and main_res["t_learned"] < main_res["t_plain"])
+    t_val = main_res["t_learned"] if use_learned else main_res["t_plain"]
+    value = video.px / t_val / 1e6
 
-    cpu = None
-    if args.cpu_frames > 0:
-        print(f"[bench] oracle on {args.cpu_frames} frame(s)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(clip, w["G"], w["P"], min(args.cpu_frames, F))
+    extras = {}
+    for name, c in extra_clips.items():
+        if name == "batch_16_mixed":
+            extras[name] = bench_batch(args, c)
+        else:
+            r = bench_video(argparse.Namespace(steps=max(1, min(args.steps, 3)), warmup=1), c, name, learned=False)
+            extras[name] = dict(mpx_s=round(r["plain_mpx"], 2), frames=c.nframes, roofline=r["roofline"],
+                                frame_roofline=r["frame_roofline"])
+
+    cpu = cpu96 = None
+    if args.cpu == "on":
+        log("oracle on one full-size frame")
+        cpu = oracle_rate(clip, w["G"], w["P"], 1, "full-size sample")
+        if args.workload == "video_1920x1080_k10":
+            small = downsample_clip(clip, 20)
+            cpu96 = oracle_rate(small, w["G"], w["P"], small.nframes, "the clip's 96x54 area-averaged copy")
 
     out = {
-        "metric": "decomposed Mpixel/s at fixed final energy (1 GPU); learned warm-start vs plain",
+        "metric": METRIC,
         "value": round(value, 2),
         "unit": "Mpx/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(t_val * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (f64 reductions)",
         "data": "synthetic",
-        "config": {"workload": args.workload, "width": W_, "height": H_, "frames": F, "K": K,
-                   "gn_iters": w["G"], "pcg_iters": w["P"], "temporal": bool(w["temporal"]),
-                   "refine": "every", "method": "plain", "graph": not args.no_graph},
-        "roofline": roofline,
+        "config": {"workload": args.workload, "width": video.W, "height": video.H, "frames": video.F, "K": video.K,
+                   "frames_timed": video.F - 1, "gn_iters": video.G, "pcg_iters": video.P, "temporal": True,
+                   "refine": "every", "graph": True,
+                   "method": "learned warm start + energy-target continuation" if use_learned else "plain"},
+        "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
-        "learned_vs_plain": learned,
-        "frame_roofline": dict(achieved=round(frame_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                               frac=round(frame_gbs / HBM_PEAK_GBS, 4),
-                               algorithmic_bytes_per_frame=ab["frame"] * W_ * H_),
-        "gpu_event_ms_per_step": round(gpu_ms / args.steps, 3),
-        "final_energy_last_frame": stats["energy_final"],
-        "kernels": kernels,
+        "cpu_baseline_96x54_copy": cpu96,
+        "plain_mpx_s": round(main_res["plain_mpx"], 2),
+        "learned_vs_plain": lv,
+        "frame_roofline": main_res["frame_roofline"],
+        "kernels": main_res["kernels"],
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
-    solver.close()
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy: 5 x {nbytes} bytes read and written", file=sys.stderr, flush=True)
+        log(f"calibration copy: 5 x {nbytes} bytes read and written")
     return 0
 
 

@@ -137,14 +137,30 @@ gid_status gid_reset_clip(gid_ctx *ctx);
  * The first frame of a clip starts from r = ln b_id, T_0 = clip(|I|/|R|, 0, 4),
  * T_k = 0.01; later frames start from the previous frame's result and, with
  * params.temporal, add the consistency prior against it.
+ * A frame is pending from this call until gid_synchronize; a second frame (or
+ * gid_load_frame) before that returns GID_ERR_STATE, so every frame's status
+ * reaches the caller and a rejected first frame never seeds the next one.
  * Errors: GID_ERR_INVALID_ARG (NULL frame or ids), GID_ERR_STATE (no base
- * colours set), GID_ERR_HIP. */
+ * colours set, or a frame pending), GID_ERR_HIP. */
 gid_status gid_decompose_frame(gid_ctx *ctx, const float *frame_dev, const uint8_t *cluster_ids_dev,
                                float *layers_dev, double *base_colors_host, gid_frame_stats *stats);
 
 /* Wait for the context's stream; completes pending host outputs.  Returns
  * GID_ERR_NUMERIC if the last frame's final energy is not finite. */
 gid_status gid_synchronize(gid_ctx *ctx);
+
+/* Energy-target continuation (used by the learned warm start's matched-energy
+ * runs; not part of the paper's fixed schedule of Sec. 7.1).  With target > 0
+ * every following frame runs up to max_gn (1..64) outer iterations instead of
+ * params.gn_iters and evaluates E of Sec. 6 after each one; once E <= target the
+ * frame's remaining iterations are skipped on the device, with no host round
+ * trip.  gid_frame_stats.gn_done then reports the iterations run and
+ * energy_half their energies (n_half = gn_done); energy_final is the energy after
+ * the last iteration run.  Call it between frames: target applies to every
+ * following frame until changed; target <= 0 restores the fixed schedule.
+ * Errors: GID_ERR_INVALID_ARG (NaN target, max_gn outside 1..64),
+ * GID_ERR_STATE (a frame is pending). */
+gid_status gid_set_energy_target(gid_ctx *ctx, double target, int32_t max_gn);
 
 /* ---- single-step access (each step of the schedule on the current frame) ----
  * These run one step of the hot path on the frame loaded by gid_load_frame and

@@ -21,7 +21,7 @@ using namespace gid;
 
 namespace {
 
-constexpr int FINAL_SLOT = ELOG_SLOTS - 2;   // energy of the frame when half-steps are not recorded
+constexpr int FINAL_SLOT = ELOG_FINAL_SLOT;
 constexpr int PROBE_SLOT = ELOG_SLOTS - 1;   // single-step energy evaluation
 constexpr int NSTATS = NSCAL + ELOG_SLOTS * ELOG_STRIDE + 3 * KMAX;   // doubles of the statistics block
 constexpr int NB_MAX = 2048;                 // default cap on workgroups of a per-pixel launch (one tile each up to here)
@@ -65,8 +65,14 @@ struct gid_ctx {
     gid_frame_stats* pend_stats = nullptr;
     int pend_nhalf = 0, pend_final_slot = FINAL_SLOT, pend_frame = 0, pend_gn = 0;
     bool pend_had_prev = false;
-    // replayable schedules keyed by (refine, temporal, record)
-    hipGraphExec_t graphs[8] = {};
+    bool pend_target = false;
+    // energy-target continuation: target > 0 runs up to target_gn outer
+    // iterations and stops the frame on the device once E <= target
+    double target = 0.0;
+    int target_gn = 0;
+    double* h_target = nullptr;    // pinned slot the target is uploaded from
+    // replayable schedules keyed by (refine, temporal, record, energy target)
+    hipGraphExec_t graphs[16] = {};
     hipStream_t cap_stream = nullptr;
     // kernel timing
     bool profiling = false;
@@ -285,10 +291,14 @@ bool colours_valid(const double* b, int nk) {
 // Enqueue the G outer iterations of one frame (everything between the per-frame
 // precompute and the output pass) through launch(kern, step); used for one clip
 // and for batches.  Returns the number of energy slots used.
+// With check (energy-target mode) the energy is evaluated after every outer
+// iteration into slot g and compared with the frame's target on the device.
 template <typename LaunchFn>
-hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& launch, int* nslots) {
+hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& launch, int* nslots,
+                            bool check = false) {
     int slot = 0;
     hipError_t e = hipSuccess;
+    if (check) record = false;
     for (int g = 0; g < G; ++g) {
         Step s{};
         s.gn = g;
@@ -315,6 +325,16 @@ hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& l
                 if ((e = launch(KN_ENERGY_FINISH, s)) != hipSuccess) return e;
             }
         }
+        if (check) {
+            s.slot = g;
+            s.check = 1;
+            if ((e = launch(KN_ENERGY, s)) != hipSuccess) return e;
+            if ((e = launch(KN_ENERGY_FINISH, s)) != hipSuccess) return e;
+        }
+    }
+    if (check) {
+        *nslots = 0;
+        return hipSuccess;
     }
     if (!record) {
         Step s{};
@@ -327,8 +347,9 @@ hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& l
 }
 
 hipError_t enqueue_outer(gid_ctx* c, hipStream_t st, const Args& base, bool refine, bool record, int* nslots) {
-    return enqueue_schedule(c->prm.gn_iters, c->prm.pcg_iters, refine, record,
-                            [&](Kern k, const Step& s) { return L1(c, st, k, base, s); }, nslots);
+    const bool check = c->target > 0.0;
+    return enqueue_schedule(check ? c->target_gn : c->prm.gn_iters, c->prm.pcg_iters, refine, record,
+                            [&](Kern k, const Step& s) { return L1(c, st, k, base, s); }, nslots, check);
 }
 
 // Capture a schedule into a graph on a private stream (the caller's may be the
@@ -355,7 +376,7 @@ gid_status run_outer(gid_ctx* c, const Args& base, bool refine, bool record, int
         GID_HIP(c, enqueue_outer(c, c->stream, base, refine, record, nslots));
         return GID_OK;
     }
-    const int key = (refine ? 1 : 0) | (base.temporal ? 2 : 0) | (record ? 4 : 0);
+    const int key = (refine ? 1 : 0) | (base.temporal ? 2 : 0) | (record ? 4 : 0) | (c->target > 0.0 ? 8 : 0);
     if (!c->graphs[key]) {
         hipGraphExec_t ex = nullptr;
         hipError_t e = capture_graph(&c->cap_stream, [&](hipStream_t cs) {
@@ -364,7 +385,7 @@ gid_status run_outer(gid_ctx* c, const Args& base, bool refine, bool record, int
         if (e != hipSuccess) return fail(c, GID_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
         c->graphs[key] = ex;
     } else {
-        *nslots = record ? (c->prm.gn_iters * (refine ? 2 : 1)) : 0;
+        *nslots = (record && !(c->target > 0.0)) ? (c->prm.gn_iters * (refine ? 2 : 1)) : 0;
     }
     GID_HIP(c, hipGraphLaunch(c->graphs[key], c->stream));
     return GID_OK;
@@ -399,7 +420,7 @@ void release(gid_ctx* c) {
     c->cap_stream = nullptr;
     if (c->arena) (void)hipFree(c->arena);
     if (c->h_scal) (void)hipHostFree(c->h_scal);   // h_elog and h_b64 point into the same block
-    if (c->h_small) (void)hipHostFree(c->h_small);
+    if (c->h_small) (void)hipHostFree(c->h_small);   // h_target points into the same block
     if (c->warena) (void)hipFree(c->warena);
     c->warena = nullptr;
     c->arena = nullptr;
@@ -528,13 +549,14 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     c->bsum = reinterpret_cast<double*>(base + o_bsum);
     c->partials = reinterpret_cast<double*>(base + o_part);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_scal), sizeof(double) * NSTATS) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->h_small), sizeof(double) * 8 * 3 * KMAX) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_small), sizeof(double) * (8 * 3 * KMAX + 1)) != hipSuccess) {
         release(c);
         delete c;
         return GID_ERR_OUT_OF_MEMORY;
     }
     c->h_elog = c->h_scal + NSCAL;
     c->h_b64 = c->h_elog + ELOG_SLOTS * ELOG_STRIDE;
+    c->h_target = c->h_small + 8 * 3 * KMAX;
     // zero the whole workspace once (tickets must start at zero)
     if (hipMemsetAsync(c->arena, 0, off, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
         release(c);
@@ -647,8 +669,14 @@ gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* id
                                double* b_out, gid_frame_stats* stats) {
     if (!c) return GID_ERR_INVALID_ARG;
     if (!frame || !ids) return fail(c, GID_ERR_INVALID_ARG, "frame and cluster ids are required");
+    if (c->pending) return fail(c, GID_ERR_STATE, "the previous frame is pending: call gid_synchronize first");
     gid_status s = check_frame_ready(c);
     if (s != GID_OK) return s;
+    if (c->target > 0.0) {
+        // the pinned slot is not touched again before gid_synchronize
+        *c->h_target = c->target;
+        GID_HIP(c, hipMemcpyAsync(c->scal + S_TARGET, c->h_target, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    }
     Args a;
     if ((s = load_frame_impl(c, frame, ids, a)) != GID_OK) return s;
     const bool judged = c->wnet != nullptr && c->have_prev;
@@ -666,13 +694,32 @@ gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* id
     c->pend_b = b_out;
     c->pend_stats = stats;
     c->pend_nhalf = nslots;
-    c->pend_final_slot = record ? nslots - 1 : FINAL_SLOT;
+    c->pend_target = c->target > 0.0;
+    c->pend_final_slot = (record && !c->pend_target) ? nslots - 1 : FINAL_SLOT;
     c->pend_frame = c->frame_index;
     c->pend_gn = c->prm.gn_iters;
     c->pend_had_prev = c->have_prev;
     c->pend_judged = judged;
     c->frame_index += 1;
     c->have_prev = true;
+    return GID_OK;
+}
+
+gid_status gid_set_energy_target(gid_ctx* c, double target, int32_t max_gn) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (std::isnan(target) || (target > 0.0 && (max_gn < 1 || max_gn > 64)))
+        return fail(c, GID_ERR_INVALID_ARG, "energy target must not be NaN and max_gn must be in 1..64");
+    if (c->pending) return fail(c, GID_ERR_STATE, "the previous frame is pending: call gid_synchronize first");
+    const int gn = target > 0.0 ? max_gn : 0;
+    if (gn != c->target_gn) {   // the target-mode schedule is captured for one iteration count
+        for (int k = 8; k < 16; ++k)
+            if (c->graphs[k]) {
+                (void)hipGraphExecDestroy(c->graphs[k]);
+                c->graphs[k] = nullptr;
+            }
+    }
+    c->target = target > 0.0 ? target : 0.0;
+    c->target_gn = gn;
     return GID_OK;
 }
 
@@ -696,11 +743,12 @@ gid_status gid_synchronize(gid_ctx* c) {
         std::memset(st, 0, sizeof(*st));
         st->energy_final = fin[0];
         for (int v = 0; v < NTERMS; ++v) st->energy_terms[v] = fin[1 + v];
-        st->n_half = c->pend_nhalf;
-        for (int h = 0; h < c->pend_nhalf && h < GID_MAX_HALF_STEPS; ++h)
+        const int gn_done = c->pend_target ? (int)c->h_scal[S_GN_DONE] : c->pend_gn;
+        st->n_half = c->pend_target ? gn_done : c->pend_nhalf;
+        for (int h = 0; h < st->n_half && h < GID_MAX_HALF_STEPS; ++h)
             st->energy_half[h] = c->h_elog[(long long)h * ELOG_STRIDE];
         for (int g = 0; g < 64; ++g) st->pcg_rz_last[g] = c->h_scal[S_RZ_LOG + g];
-        st->gn_done = c->pend_gn;
+        st->gn_done = gn_done;
         st->pcg_breakdowns = (int32_t)c->h_scal[S_BREAKDOWNS];
         st->bstep_rejected = (int32_t)c->h_scal[S_BREJECT];
         st->frame_index = c->pend_frame;
@@ -718,6 +766,7 @@ gid_status gid_synchronize(gid_ctx* c) {
 gid_status gid_load_frame(gid_ctx* c, const float* frame, const uint8_t* ids) {
     if (!c) return GID_ERR_INVALID_ARG;
     if (!frame || !ids) return fail(c, GID_ERR_INVALID_ARG, "frame and cluster ids are required");
+    if (c->pending) return fail(c, GID_ERR_STATE, "the previous frame is pending: call gid_synchronize first");
     gid_status s = check_frame_ready(c);
     if (s != GID_OK) return s;
     Args a;
@@ -1042,8 +1091,11 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
                                float* const* layers) {
     if (!b || !frames || !ids) return bfail(b, GID_ERR_INVALID_ARG, "frames and ids are required");
     if (b->pending) return bfail(b, GID_ERR_STATE, "synchronize the previous batch step first");
-    for (gid_ctx* c : b->clips)
+    for (gid_ctx* c : b->clips) {
         if (c->wnet) return bfail(b, GID_ERR_UNSUPPORTED, "batched clips run without a learned warm start");
+        if (c->target > 0.0) return bfail(b, GID_ERR_UNSUPPORTED, "batched clips run the fixed schedule (no energy target)");
+        if (c->pending) return bfail(b, GID_ERR_STATE, "a clip has a pending single frame: synchronize it first");
+    }
     const int n = (int)b->clips.size();
     std::vector<int> act;
     unsigned long long mask = 0;

@@ -21,6 +21,7 @@ constexpr int ELOG_STRIDE = 1 + NTERMS;   // total + terms per energy slot
 constexpr int ELOG_SLOTS = GID_MAX_HALF_STEPS + 4;
 constexpr int JUDGE_PREV_SLOT = ELOG_SLOTS - 4;    // warm-start judge: energy at the previous frame's result
 constexpr int JUDGE_NET_SLOT = ELOG_SLOTS - 3;     // warm-start judge: energy at the network's prediction
+constexpr int ELOG_FINAL_SLOT = ELOG_SLOTS - 2;    // the frame's final energy when half-steps are not recorded
 constexpr int NB_TUNE_MAX = 2048;   // workgroups of a per-pixel launch (at most)
 constexpr int NB_BS_MAX = 512;   // workgroups of the apply + base-colour-sum pass (at most)
 
@@ -34,6 +35,9 @@ enum Scal : int {
     S_BADIN,        // non-finite frame values or out-of-range ids in this frame's input
     S_CAND_OK,      // 1 if the network's colour prediction is admissible (every component in (1e-4, inf))
     S_LEARNED,      // 1 if the judge kept the network's prediction as this frame's start
+    S_DONE,         // 1 once the frame reached its energy target (its remaining iterations are no-ops)
+    S_GN_DONE,      // outer iterations completed in this frame (energy-target mode)
+    S_TARGET,       // the frame's energy target (set by the host before the frame; not reset)
     S_RZ_LOG,       // first of 64 slots: final <r, z> of each layer step
     NSCAL = S_RZ_LOG + 64
 };
@@ -63,6 +67,7 @@ struct Step {
     int add_delta;  // apply pass: u += delta (0: sums only)
     int log_rz;     // apply pass: record the final <r, z> of the layer step
     int debug;      // single-step access: skip scalar bookkeeping / use caller buffers
+    int check;      // energy total: compare with the frame's target after an outer iteration
 };
 
 // One clip: its geometry, parameters and every buffer a kernel may touch.

@@ -204,6 +204,10 @@ __device__ __forceinline__ void for_each_pixel(const Args& a, const Lc& lc, F&& 
 
 __device__ __forceinline__ bool lead_thread(const Lc& lc) { return lc.lb == 0 && threadIdx.x == 0; }
 
+// Nothing left to do in this frame: its input was rejected, or it reached its
+// energy target (uniform over the grid: both flags change only between launches).
+__device__ __forceinline__ bool frame_idle(const Args& a) { return a.scal[S_BADIN] != 0.0 || a.scal[S_DONE] != 0.0; }
+
 // Basis with the white illuminant first, and the basis minus its channel mean.
 // Both come from device tables with uniform addresses, so they live in scalar
 // registers (the base-colour solve and the colour upload maintain the tables).
@@ -257,6 +261,8 @@ __device__ __forceinline__ void scan_body(const Args& a, const Lc& lc, const Ste
         a.scal[S_BREJECT] = 0.0;
         a.scal[S_STOP] = 0.0;
         a.scal[S_BADIN] = 0.0;
+        a.scal[S_DONE] = 0.0;
+        a.scal[S_GN_DONE] = 0.0;
         for (int g = 0; g < 64; ++g) a.scal[S_RZ_LOG + g] = 0.0;
     }
     const long long ps = a.ps;
@@ -437,7 +443,7 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
     constexpr int N = K + 4;
     double* sh4 = reinterpret_cast<double*>(smem);
     float* Ul = reinterpret_cast<float*>(smem + 32);
-    if (a.scal[S_BADIN] != 0.0) return;
+    if (frame_idle(a)) return;
     Basis<K> bs;
     bs.load(a.bf, a.bcf);
     const Lam L = a.lam;
@@ -595,7 +601,7 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
     Basis<K> bs;
     bs.load(a.bf, a.bcf);
     const bool dbg = st.debug != 0;
-    if (!dbg && (a.scal[S_STOP] != 0.0 || a.scal[S_BADIN] != 0.0)) return;   // uniform over the grid
+    if (!dbg && (a.scal[S_STOP] != 0.0 || frame_idle(a))) return;   // uniform over the grid
     const int it = st.iter;
     const bool first = dbg || it == 0;
     double alpha = 0.0;
@@ -861,7 +867,7 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
     double* red = reinterpret_cast<double*>(smem + 32 + 6 * BS_STRIDE * 8);
     float (*Ts)[BS_STRIDE] = reinterpret_cast<float (*)[BS_STRIDE]>(smem + 32 + 6 * BS_STRIDE * 8 +
                                                                       NG * 3 * K * (K + 1) * 8);
-    if (a.scal[S_BADIN] != 0.0) return;
+    if (frame_idle(a)) return;
     // x += alpha p of the last PCG iteration (st.iter), applied with the layer step
     // u += x; without PCG iterations x is zero and <r0, z0> is logged
     double alpha = 0.0;
@@ -1091,7 +1097,7 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
     double* sums = reinterpret_cast<double*>(smem);
     double (*Hm)[NN + 1] = reinterpret_cast<double (*)[NN + 1]>(smem + 8 * NS);
     double* gv = reinterpret_cast<double*>(smem + 8 * (NS + NN * (NN + 1)));
-    if (a.scal[S_BADIN] != 0.0) return;
+    if (frame_idle(a)) return;
     const double* part = a.partials + (long long)R_BS * a.part_stride;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
     // U sums per wavefront per round, every partial of a sum in one unrolled batch
@@ -1245,7 +1251,7 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
 template <int K>
 __device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     double* sh4 = reinterpret_cast<double*>(smem);
-    if (a.scal[S_BADIN] != 0.0) return;
+    if (frame_idle(a)) return;
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
     double e[NTERMS];
@@ -1350,7 +1356,7 @@ __device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const S
 __device__ __forceinline__ void energy_finish_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     const int nb = a.nblocks;
     double* sh4 = reinterpret_cast<double*>(smem);
-    if (a.scal[S_BADIN] != 0.0) return;
+    if (frame_idle(a)) return;
     double tot[NTERMS];
     site_totals<NTERMS>(a, R_EN, nb, sh4, tot);
     if (threadIdx.x == 0) {
@@ -1361,6 +1367,14 @@ __device__ __forceinline__ void energy_finish_body(const Args& a, const Lc& lc, 
             s += tot[v];
         }
         slot[0] = s;
+        if (st.check) {
+            // energy-target mode: this outer iteration is done; its energy is
+            // also the frame's final energy unless a later iteration runs
+            double* fin = a.elog + (long long)ELOG_FINAL_SLOT * ELOG_STRIDE;
+            for (int v = 0; v <= NTERMS; ++v) fin[v] = slot[v];
+            a.scal[S_GN_DONE] += 1.0;
+            if (s <= a.scal[S_TARGET]) a.scal[S_DONE] = 1.0;
+        }
     }
 }
 
@@ -1370,6 +1384,8 @@ template <int K>
 __device__ __forceinline__ void output_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int N = K + 4;
     if (a.scal[S_BADIN] != 0.0) return;
+    // the frame is over: single-step calls after it must not see its stop flag
+    if (lead_thread(lc)) a.scal[S_DONE] = 0.0;
     const long long ps = a.ps;
     for_each_pixel(a, lc, [&](int x, int y, long long i) {
         // every load ahead of the stores, which the compiler may not move them past

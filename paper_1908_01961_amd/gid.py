@@ -72,6 +72,7 @@ SIGNATURES = [
     ("gid_decompose_frame", c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double),
                                       POINTER(GidFrameStats)]),
     ("gid_synchronize", c_int32, [c_void_p]),
+    ("gid_set_energy_target", c_int32, [c_void_p, c_double, c_int32]),
     ("gid_load_frame", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("gid_set_state", c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     ("gid_set_prev_frame", c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -229,13 +230,20 @@ class Solver:
         f = _ptr(frame, torch.float32, (3, self.H, self.W), "frame")
         i = _ptr(ids, torch.uint8, (self.H, self.W), "ids")
         lp = _ptr(layers, torch.float32, (self.n, self.H, self.W), "layers") if layers is not None else None
-        self._b = np.zeros(3 * self.K)
-        self._check(self.lib.gid_decompose_frame(self.h, f, i, lp, self._b.ctypes.data_as(POINTER(c_double)),
+        # a refused call leaves the pending frame's output buffer in place
+        bout = np.zeros(3 * self.K)
+        self._check(self.lib.gid_decompose_frame(self.h, f, i, lp, bout.ctypes.data_as(POINTER(c_double)),
                                                  byref(self._stats)), "gid_decompose_frame")
+        self._b = bout
 
     def synchronize(self):
         self._check(self.lib.gid_synchronize(self.h), "gid_synchronize")
         return self._b.reshape(self.K, 3).copy(), self._stats.to_dict()
+
+    def set_energy_target(self, target: float, max_gn: int = 0):
+        """Stop each following frame once its energy is <= target (up to max_gn
+        outer iterations); target <= 0 restores the fixed schedule."""
+        self._check(self.lib.gid_set_energy_target(self.h, float(target), int(max_gn)), "gid_set_energy_target")
 
     def decompose_frame(self, frame, ids, layers=None):
         self.decompose_frame_async(frame, ids, layers)
