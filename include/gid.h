@@ -130,7 +130,10 @@ gid_status gid_reset_clip(gid_ctx *ctx);
 
 /* Decompose one frame (Sec. 7.1 schedule).
  *   frame_dev       3 planes float32 (device), read during the call's stream work
- *   cluster_ids_dev width*height uint8 (device), values in [0, K)
+ *   cluster_ids_dev width*height uint8 (device), values in [0, K); NULL assigns every
+ *                   pixel to the current base colour of nearest chromaticity (squared
+ *                   L2 in FP64, ties to the lowest index), the rule of Sec. 5.1 against
+ *                   the refined colours, for the frames after the clustered first one
  *   layers_dev      K+4 planes float32 (device) written: R_r, R_g, R_b, T_0..T_K; may be NULL
  *   base_colors_host K x 3 double written after gid_synchronize; may be NULL
  *   stats           filled after gid_synchronize; may be NULL
@@ -140,7 +143,7 @@ gid_status gid_reset_clip(gid_ctx *ctx);
  * A frame is pending from this call until gid_synchronize; a second frame (or
  * gid_load_frame) before that returns GID_ERR_STATE, so every frame's status
  * reaches the caller and a rejected first frame never seeds the next one.
- * Errors: GID_ERR_INVALID_ARG (NULL frame or ids), GID_ERR_STATE (no base
+ * Errors: GID_ERR_INVALID_ARG (NULL frame), GID_ERR_STATE (no base
  * colours set, or a frame pending), GID_ERR_HIP. */
 gid_status gid_decompose_frame(gid_ctx *ctx, const float *frame_dev, const uint8_t *cluster_ids_dev,
                                float *layers_dev, double *base_colors_host, gid_frame_stats *stats);
@@ -348,6 +351,30 @@ const char *gid_net_last_error(const gid_net *net);
  * network must match the context's width, height and K and enqueue on the same
  * stream.  Errors: GID_ERR_INVALID_ARG, GID_ERR_OUT_OF_MEMORY. */
 gid_status gid_set_warmstart(gid_ctx *ctx, gid_net *net);
+
+/* ---- base-colour initialisation (Sec. 5.1, chromaticity clustering) ----
+ * Cluster a clip's first frame: a histogram of its chromaticity C = I / |I|
+ * (|.| the channel mean) with 10 partitions per axis over [0, 3], weighted
+ * k-means on the bin mid-points (populations as weights, at most k_max
+ * centres; seeded with the most populated bin, then the farthest non-empty
+ * bin), centres closer than merge_dist merged (the smaller cluster joins the
+ * larger; the paper uses 0.2), every pixel assigned to its nearest centre and
+ * the mean RGB of each cluster's pixels returned as its initial base colour.
+ *   frame_dev    3 planes width*height float32 (device)
+ *   k_max        upper bound on the clusters, 1..16 (the paper uses 10)
+ *   hip_stream   stream to enqueue on (NULL = null stream); the call is synchronous
+ *   ids_dev      width*height uint8 (device) written: the pixel's cluster, 0..*k_out-1
+ *   colors_host  k_max x 3 doubles written (rows below *k_out): mean RGB per cluster
+ *   centres_host k_max x 3 doubles (may be NULL): the centres in chromaticity
+ *   k_out        number of clusters found
+ * The ids and colours go to gid_set_base_colors / gid_decompose_frame with K =
+ * *k_out.  Allocates (and frees) a device scratch buffer of at most
+ * GID_CLUSTER_SCRATCH_BYTES.  Errors: GID_ERR_INVALID_ARG, GID_ERR_NUMERIC (a
+ * non-finite frame value; nothing written), GID_ERR_OUT_OF_MEMORY, GID_ERR_HIP. */
+#define GID_CLUSTER_SCRATCH_BYTES 2621440u
+gid_status gid_cluster_frame(const float *frame_dev, int32_t width, int32_t height, int32_t k_max,
+                             double merge_dist, void *hip_stream, uint8_t *ids_dev, double *colors_host,
+                             double *centres_host, int32_t *k_out);
 
 const char *gid_status_string(gid_status s);
 /* Last error message of this context (valid until its next call). */

@@ -15,6 +15,7 @@ Everything is NumPy/SciPy in float64.  Modules:
   explicit   -- row-by-row residual vector and sparse Jacobian, direct solve
   basecolor  -- the base-colour (B-)step normal equations and SVD solve
   schedule   -- initialisation, the per-frame alternating schedule, video loop
+  clustering -- base-colour initialisation by chromaticity clustering (Sec. 5.1)
 """
 from .params import OracleParams, default_params
 from .energy import (FrameData, prepare_frame, energy_terms, total_energy, chromaticity,
@@ -24,11 +25,12 @@ from .gauss_newton import (Linearisation, linearise, apply_normal, rhs, jacobi_d
 from .explicit import assemble_residuals, direct_step
 from .basecolor import bstep_sums, bstep_system, bstep_solve
 from .schedule import init_state, decompose_frame, decompose_clip, FrameResult
+from .clustering import cluster_frame, nearest_ids
 
 __all__ = [
     "OracleParams", "default_params", "FrameData", "prepare_frame", "energy_terms",
     "total_energy", "chromaticity", "delta_chroma", "soft_retinex_weight", "Linearisation",
     "linearise", "apply_normal", "rhs", "jacobi_diag", "pcg", "surrogate_energy",
     "assemble_residuals", "direct_step", "bstep_sums", "bstep_system", "bstep_solve",
-    "init_state", "decompose_frame", "decompose_clip", "FrameResult",
+    "init_state", "decompose_frame", "decompose_clip", "FrameResult", "cluster_frame", "nearest_ids",
 ]

@@ -19,6 +19,7 @@ from typing import Optional
 import numpy as np
 
 from .basecolor import bstep
+from .clustering import nearest_ids
 from .energy import FrameData, cluster_log_reflectance, intensity, prepare_frame, total_energy
 from .explicit import direct_step
 from .gauss_newton import linearise, pcg
@@ -62,9 +63,13 @@ def decompose_frame(I, ids, b, b_init, p: OracleParams, G: int, P: int, *, u0=No
 
     prev: (C_prev, r_prev) of the previous frame for the temporal prior, or None.
     solver: "pcg" (P Jacobi-PCG iterations) or "direct" (exact normal-equation solve).
+    ids None: every pixel takes the base colour of nearest chromaticity at the
+    frame's start (the assignment rule of Sec. 5.1 against the current colours).
     """
-    fd = prepare_frame(I, ids, p, *(prev if prev is not None else (None, None)))
     b = np.asarray(b, np.float64).copy()
+    if ids is None:
+        ids = nearest_ids(I, b, p)
+    fd = prepare_frame(I, ids, p, *(prev if prev is not None else (None, None)))
     u = store(init_state(fd.I, fd.ids, b), p) if u0 is None else np.asarray(u0, np.float64).copy()
     energies, infos, starts = [], [], []
     for _ in range(G):
@@ -104,7 +109,7 @@ def decompose_clip(frames, ids, b_init, p: OracleParams, G: int, P: int, *, temp
     out = []
     for t in range(F):
         refine = refine_mode == "every" or (refine_mode == "first" and t == 0)
-        res = decompose_frame(frames[t], ids[t], b, b_init, p, G, P, u0=u,
+        res = decompose_frame(frames[t], None if ids is None or ids[t] is None else ids[t], b, b_init, p, G, P, u0=u,
                               prev=prev if temporal else None, refine=refine, solver=solver,
                               record=record, keep_starts=keep_starts)
         out.append(res)

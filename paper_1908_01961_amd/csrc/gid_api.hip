@@ -668,7 +668,7 @@ gid_status gid_set_warmstart(gid_ctx* c, gid_net* net) {
 gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* ids, float* layers,
                                double* b_out, gid_frame_stats* stats) {
     if (!c) return GID_ERR_INVALID_ARG;
-    if (!frame || !ids) return fail(c, GID_ERR_INVALID_ARG, "frame and cluster ids are required");
+    if (!frame) return fail(c, GID_ERR_INVALID_ARG, "a frame is required");
     if (c->pending) return fail(c, GID_ERR_STATE, "the previous frame is pending: call gid_synchronize first");
     gid_status s = check_frame_ready(c);
     if (s != GID_OK) return s;
@@ -765,7 +765,7 @@ gid_status gid_synchronize(gid_ctx* c) {
 
 gid_status gid_load_frame(gid_ctx* c, const float* frame, const uint8_t* ids) {
     if (!c) return GID_ERR_INVALID_ARG;
-    if (!frame || !ids) return fail(c, GID_ERR_INVALID_ARG, "frame and cluster ids are required");
+    if (!frame) return fail(c, GID_ERR_INVALID_ARG, "a frame is required");
     if (c->pending) return fail(c, GID_ERR_STATE, "the previous frame is pending: call gid_synchronize first");
     gid_status s = check_frame_ready(c);
     if (s != GID_OK) return s;

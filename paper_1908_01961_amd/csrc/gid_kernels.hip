@@ -271,7 +271,7 @@ __device__ __forceinline__ void scan_body(const Args& a, const Lc& lc, const Ste
         float v[3];
         load3(a.in_frame, ps, i, v);
         if (!isfinite(v[0]) || !isfinite(v[1]) || !isfinite(v[2])) bad += 1.0;
-        if ((int)a.in_ids[i] >= a.K) bad += 1.0;
+        if (a.in_ids && (int)a.in_ids[i] >= a.K) bad += 1.0;
     });
     const double vals[1] = {block_sum(bad, sh4)};
     publish(a, lc, R_SCAN, vals, 1);
@@ -321,6 +321,25 @@ __device__ __forceinline__ double cdist(const double* a, const double* b) {
     return sqrt((d0 * d0 + d1 * d1) + d2 * d2);
 }
 
+// Index of the colour chromaticity nearest to C: squared L2 distance formed
+// d0 d0 + d1 d1 + d2 d2 left to right without contraction, ties to the lowest index.
+template <int K>
+__device__ __forceinline__ int nearest_colour(const double* C, const double (*Cb)[3]) {
+#pragma clang fp contract(off)
+    double best = INFINITY;
+    int arg = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double d0 = C[0] - Cb[k][0], d1 = C[1] - Cb[k][1], d2 = C[2] - Cb[k][2];
+        const double d = d0 * d0 + d1 * d1 + d2 * d2;
+        if (d < best) {
+            best = d;
+            arg = k;
+        }
+    }
+    return arg;
+}
+
 template <int K>
 __device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     double* sh4 = reinterpret_cast<double*>(smem);
@@ -332,16 +351,33 @@ __device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, con
     const int W = a.W, H = a.H;
     const double floor_ = a.lam.cfloor;
     const float* F = a.in_frame;
+    // without caller ids: the base colour of nearest chromaticity (Sec. 5.1's
+    // assignment rule against the current colours)
+    double Cb[K][3];
+    if (!a.in_ids) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double* b = a.b64 + 3 * k;
+            const double m = (b[0] + b[1] + b[2]) / 3.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Cb[k][c] = b[c] / m;
+        }
+    }
     for_each_pixel(a, lc, [&](int x, int y, long long i) {
         float Iv[3];
         load3(F, ps, i, Iv);
         a.I[i] = Iv[0];
         a.I[ps + i] = Iv[1];
         a.I[2 * ps + i] = Iv[2];
-        const uint8_t id = a.in_ids[i];
-        a.ids[i] = id;
         double C[3], Cn[3];
         chroma64v(Iv[0], Iv[1], Iv[2], floor_, C);
+        uint8_t id;
+        if (a.in_ids) {
+            id = a.in_ids[i];
+        } else {
+            id = (uint8_t)nearest_colour<K>(C, Cb);
+        }
+        a.ids[i] = id;
         // the four neighbours (right, left, down, up), loaded unconditionally
         const bool hn[4] = {x + 1 < W, x > 0, y + 1 < H, y > 0};
         const long long jn[4] = {hn[0] ? i + 1 : i, hn[1] ? i - 1 : i, hn[2] ? i + W : i, hn[3] ? i - W : i};

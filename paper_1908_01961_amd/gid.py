@@ -109,6 +109,8 @@ SIGNATURES = [
     ("gid_net_layer_wgrad", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_float), POINTER(c_float)]),
     ("gid_net_last_error", ctypes.c_char_p, [c_void_p]),
     ("gid_set_warmstart", c_int32, [c_void_p, c_void_p]),
+    ("gid_cluster_frame", c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,
+                                    POINTER(c_double), POINTER(c_double), POINTER(c_int32)]),
     ("gid_status_string", ctypes.c_char_p, [c_int32]),
     ("gid_last_error", ctypes.c_char_p, [c_void_p]),
 ]
@@ -173,6 +175,28 @@ def _dbl(arr, n):
     return a, a.ctypes.data_as(POINTER(c_double))
 
 
+def cluster_frame(frame, k_max: int = 10, merge_dist: float = 0.2, stream=None):
+    """Base-colour initialisation of a clip from its first frame (Sec. 5.1):
+    returns (ids uint8 tensor (H, W) on the frame's device, colours (k, 3) FP64,
+    centres (k, 3) FP64)."""
+    import torch
+    lib = load_library()
+    H, W = int(frame.shape[1]), int(frame.shape[2])
+    f = _ptr(frame, torch.float32, (3, H, W), "frame")
+    ids = torch.empty((H, W), dtype=torch.uint8, device=frame.device)
+    cols = np.zeros(3 * k_max)
+    cen = np.zeros(3 * k_max)
+    k = c_int32(0)
+    sp = c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    st = lib.gid_cluster_frame(f, W, H, int(k_max), float(merge_dist), sp, c_void_p(ids.data_ptr()),
+                               cols.ctypes.data_as(POINTER(c_double)), cen.ctypes.data_as(POINTER(c_double)),
+                               byref(k))
+    if st != GID_OK:
+        raise GidError(st, "gid_cluster_frame")
+    n = k.value
+    return ids, cols[:3 * n].reshape(n, 3).copy(), cen[:3 * n].reshape(n, 3).copy()
+
+
 class Solver:
     """One libgid context: frames of width x height with K base colours."""
 
@@ -228,7 +252,7 @@ class Solver:
         """Enqueue one frame; outputs are valid after synchronize()."""
         import torch
         f = _ptr(frame, torch.float32, (3, self.H, self.W), "frame")
-        i = _ptr(ids, torch.uint8, (self.H, self.W), "ids")
+        i = _ptr(ids, torch.uint8, (self.H, self.W), "ids") if ids is not None else None
         lp = _ptr(layers, torch.float32, (self.n, self.H, self.W), "layers") if layers is not None else None
         # a refused call leaves the pending frame's output buffer in place
         bout = np.zeros(3 * self.K)
