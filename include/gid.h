@@ -376,6 +376,26 @@ gid_status gid_cluster_frame(const float *frame_dev, int32_t width, int32_t heig
                              double merge_dist, void *hip_stream, uint8_t *ids_dev, double *colors_host,
                              double *centres_host, int32_t *k_out);
 
+/* ---- re-synthesis for the live applications (Sec. 8.4) ----
+ * Recombine layers by the image formation of Sec. 4 with edits:
+ *     I'_c(x) = R_c(x) s_{id(x),c} (T_0(x) + sum_{k=1..K} g_k b'_{k,c} T_k(x)).
+ * Recolouring an object (Sec. 8.4.1) passes its new colour in b_new and the
+ * ratio new / old as its row of refl_scale; colour keying (Sec. 8.4.2) edits the
+ * background's row of b_new; spill suppression (Sec. 8.4.3) sets its gain to 0.
+ *   layers_dev      K+4 planes float32 (device): R_r, R_g, R_b (linear), T_0..T_K,
+ *                   the layout gid_decompose_frame writes
+ *   b_new_host      K x 3 doubles: the base colours to light with
+ *   gain_host       K floats (may be NULL: all 1)
+ *   ids_dev         width*height uint8 (device) with refl_scale_host (K x 3 floats), or
+ *                   both NULL for no reflectance edit; ids outside [0, K) keep R
+ *   out_dev         3 planes float32 (device) written
+ * Asynchronous on hip_stream (NULL = null stream); FP32 arithmetic.
+ * Errors: GID_ERR_INVALID_ARG (NULL layers / colours / output, size, K outside
+ * 1..16, ids without scales or the reverse, non-finite colours or gains), GID_ERR_HIP. */
+gid_status gid_resynthesize(const float *layers_dev, int32_t width, int32_t height, int32_t K,
+                            const double *b_new_host, const float *gain_host, const uint8_t *ids_dev,
+                            const float *refl_scale_host, void *hip_stream, float *out_dev);
+
 const char *gid_status_string(gid_status s);
 /* Last error message of this context (valid until its next call). */
 const char *gid_last_error(const gid_ctx *ctx);

@@ -93,7 +93,7 @@ struct Args {
     float* pB;               // search direction, odd iterations
     float* qA;               // M^-1 q with q = A p, even iterations
     float* qB;               // M^-1 q, odd iterations
-    float* minv;             // Jacobi preconditioner M^-1 (inverse diagonal of A)
+    float* minv;             // n planes of debug output (the Jacobi diagonal is rebuilt from u where needed)
     float* I;                // 3 planes (frame copy)
     uint8_t* ids;
     float* wsr;              // 1 plane

@@ -8,12 +8,12 @@
 // wavefronts; it covers a tile of 64 columns x (4 * ppt) rows, each wavefront one
 // row of 64 pixels, so every plane access is a 256-byte coalesced row segment.
 // Tiles are handed to workgroups XCD-aware: the hardware deals workgroup i to XCD
-// i % 8, and xcd_order() gives each XCD a contiguous band of tiles so that the
-// halo rows a tile shares with its vertical neighbours stay in that XCD's L2.
+// i % 8, and xcd_order() gives each XCD a band of tile rows whose tiles its
+// workgroups take in vertical runs, so that shared halo lines stay in its L2.
 //
-// Grids are persistent-style: at most a few workgroups per CU, each owning every
-// m-th tile of its XCD's band (one tile each while the frame has at most 2048
-// tiles), so a launch produces at most 2048 partial sums.
+// Grids are persistent-style: at most 2048 workgroups, each owning a vertical
+// run of tiles of its XCD's band (one tile each while the frame has at most
+// 2048 tiles), so a launch produces at most 2048 partial sums.
 // Every kernel is a body over (clip descriptor, launch context, step); a
 // single-clip launch runs it over its whole grid, a batched launch runs it for
 // several clips of uneven size in one grid, each workgroup finding its clip
@@ -50,16 +50,40 @@ struct Lc {
 __device__ __forceinline__ int xcd_order(int j, int nb) { return (j & 7) * (nb >> 3) + (j >> 3); }
 
 // Tiles of a workgroup.  XCD x (workgroups x m .. x m + m - 1 in xcd_order, with
-// m = nb / 8) owns the contiguous band of tiles [x ntiles / 8, (x + 1) ntiles / 8);
-// its workgroups take the band's tiles round-robin (tile t0, t0 + m, ...), so the
-// workgroups in flight on one XCD work on neighbouring tiles and share their halo
-// lines through that XCD's L2.  With one tile per workgroup this is lb itself.
+// m = nb / 8) owns the band of tile rows [x nty / 8, (x + 1) nty / 8).  The band's
+// tiles are enumerated in vertical runs: groups of G tile rows, column by column,
+// and down each column within a group; workgroup jl of the XCD takes the run of
+// G consecutive tiles [jl G, (jl + 1) G) with G = ceil(band tiles / m), i.e. one
+// column of one group.  A workgroup walks down its column, so the halo rows a
+// tile shares with the next one come from L2 (the workgroup has just read them),
+// and the workgroups in flight on one XCD hold side-by-side columns at about the
+// same height, so the halo columns they share are read close together in time
+// through that XCD's L2.  With one tile per workgroup this is raster order.
 // nb is a multiple of 8 (every per-pixel grid is).
-__device__ __forceinline__ void tiles_of(int ntiles, const Lc& lc, int& t0, int& t1, int& ts) {
+struct TileSet {
+    int c0, c1;          // logical tiles [c0, c1) of the band
+    int ry0, rows, G;    // band rows [ry0, ry0 + rows), run length
+};
+
+__device__ __forceinline__ TileSet tiles_of(const Args& a, const Lc& lc) {
     const int m = lc.nb >> 3, x = lc.lb / m, jl = lc.lb - x * m;
-    t0 = (int)(((long long)x * ntiles) >> 3) + jl;
-    t1 = (int)(((long long)(x + 1) * ntiles) >> 3);
-    ts = m;
+    TileSet s;
+    s.ry0 = (x * a.nty) >> 3;
+    s.rows = (((x + 1) * a.nty) >> 3) - s.ry0;
+    const int band = s.rows * a.ntx;
+    s.G = (band + m - 1) / m;
+    s.c0 = min(band, jl * s.G);
+    s.c1 = min(band, s.c0 + s.G);
+    return s;
+}
+
+// Tile coordinates of logical tile l of a band.
+__device__ __forceinline__ void tile_xy(const Args& a, const TileSet& s, int l, int& tx, int& ty) {
+    const int gsz = s.G * a.ntx;
+    const int grp = l / gsz, rem = l - grp * gsz;
+    const int h = min(s.G, s.rows - grp * s.G);
+    tx = rem / h;
+    ty = s.ry0 + grp * s.G + (rem - tx * h);
 }
 
 __device__ __forceinline__ Lc whole_grid() { return Lc{xcd_order((int)blockIdx.x, (int)gridDim.x), (int)gridDim.x}; }
@@ -186,14 +210,15 @@ __device__ __forceinline__ PcgScalars pcg_scalars(const Args& a, int i, int nb, 
 // Visit every pixel of this workgroup's tiles: f(x, y, i).
 template <typename F>
 __device__ __forceinline__ void for_each_pixel(const Args& a, const Lc& lc, F&& f) {
-    int t0, t1, ts;
-    tiles_of(a.ntiles, lc, t0, t1, ts);
+    const TileSet tset = tiles_of(a, lc);
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int rows = TYW * a.ppt;
-    for (int tile = t0; tile < t1; tile += ts) {
-        const int x = (tile % a.ntx) * TX + lx;
+    for (int tile = tset.c0; tile < tset.c1; ++tile) {
+        int tx, ty;
+        tile_xy(a, tset, tile, tx, ty);
+        const int x = tx * TX + lx;
         if (x >= a.W) continue;
-        const int ybase = (tile / a.ntx) * rows + ly;
+        const int ybase = ty * rows + ly;
         for (int j = 0; j < a.ppt; ++j) {
             const int y = ybase + TYW * j;
             if (y >= a.H) break;
@@ -472,6 +497,55 @@ __device__ __forceinline__ void rs_pairs_lds(const Args& a, const float* Ul, int
     wr[3] = hu ? lr * w_rs_lds(Ul, li - HW, hr, true, a.lam) : 0.0f;
 }
 
+// Reflectance R = exp(r) and shading S_c = sum_k b_kc T_k of a pixel (Sec. 4),
+// the sum as an explicit FMA chain so every kernel forms it identically.
+template <int K>
+__device__ __forceinline__ void refl_shading(const float* r, const float* T, const Basis<K>& bs, float* R, float* S) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        R[c] = expf(r[c]);
+        float sum = 0.0f;
+#pragma unroll
+        for (int k = 0; k <= K; ++k) sum = fmaf(bs.B[k][c], T[k], sum);
+        S[c] = sum;
+    }
+}
+
+// IRLS weights of the unary layer terms (Sec. 6.4): indirect sparsity (k >= 1)
+// and non-negativity (0 for T > 0, else lambda / (|T| + eps)).
+__device__ __forceinline__ float w_unary(float T, int k, const Lam& L) {
+    const float at = fabsf(T);
+    const float wis = (k > 0) ? L.is * rcp_pos(at + L.eps_irls) : 0.0f;
+    const float wnn = (T > 0.0f) ? 0.0f : L.nn * rcp_pos(at + L.eps_nn);
+    return wis + wnn;
+}
+
+// Jacobi diagonal diag(J^T J) of a pixel without its stencil terms: data,
+// clustering, temporal pairs, monochromaticity and the unary layer terms.
+// Every operation is rounded on its own (no contraction), and the stencil
+// terms are added with __fadd_rn, so that the build and the PCG iteration,
+// which both rebuild the diagonal from the staged unknowns, agree bit for bit.
+template <int K>
+__device__ __forceinline__ void diag_unary(const float* R, const float* S, const float* T, float w, float gs,
+                                           const Basis<K>& bs, const Lam& L, float* M) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float RS = __fmul_rn(R[c], S[c]);
+        M[c] = __fadd_rn(__fadd_rn(__fmul_rn(__fmul_rn(L.data, RS), RS), L.cl), __fmul_rn(L.rc, gs));
+    }
+#pragma unroll
+    for (int k = 0; k <= K; ++k) {
+        float Md = 0.0f, Mm = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float RB = __fmul_rn(R[c], bs.B[k][c]);
+            Md = __fadd_rn(Md, __fmul_rn(RB, RB));
+            Mm = __fadd_rn(Mm, __fmul_rn(bs.Bc[k][c], bs.Bc[k][c]));
+        }
+        M[3 + k] = __fadd_rn(__fadd_rn(__fmul_rn(L.data, Md), __fmul_rn(__fmul_rn(L.mo, w), Mm)), w_unary(T[k], k, L));
+    }
+}
+
 // ------------------------------------------------------------------ GN build
 
 template <int K>
@@ -488,11 +562,12 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int li = (ly + 1) * HW + lx + 1;
     const int off[4] = {1, HW, -1, -HW};
-    int t0, t1, ts;
-    tiles_of(a.ntiles, lc, t0, t1, ts);
+    const TileSet tset = tiles_of(a, lc);
     double acc = 0.0;
-    for (int tile = t0; tile < t1; tile += ts) {
-        const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TYW;
+    for (int tile = tset.c0; tile < tset.c1; ++tile) {
+        int tx, ty;
+        tile_xy(a, tset, tile, tx, ty);
+        const int x0 = tx * TX, y0 = ty * TYW;
         for (int idx = threadIdx.x; idx < HN; idx += NTHREADS) {
             const int gx = x0 + idx % HW - 1, gy = y0 + idx / HW - 1;
             const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
@@ -517,23 +592,17 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
             const int id = a.ids[i];
             const float w = a.wsr[i];
             float R[3], S[3], e[3];
+            refl_shading<K>(r, T, bs, R, S);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                R[c] = expf(r[c]);
-                float sum = 0.0f;
-#pragma unroll
-                for (int k = 0; k <= K; ++k) sum += bs.B[k][c] * T[k];
-                S[c] = sum;
-                e[c] = Iv[c] - R[c] * sum;
-            }
+            for (int c = 0; c < 3; ++c) e[c] = Iv[c] - R[c] * S[c];
             float g[N], M[N];
             const float gs = a.temporal ? a.tg[i] : 0.0f;
+            diag_unary<K>(R, S, T, w, gs, bs, L, M);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float RS = R[c] * S[c];
                 const float tgr = a.temporal ? a.tg[(1 + c) * ps + i] : 0.0f;
                 g[c] = L.data * RS * e[c] - L.cl * (r[c] - a.lnb[3 * id + c]) - L.rc * (gs * r[c] - tgr);
-                M[c] = L.data * RS * RS + L.cl + L.rc * gs;
             }
             const float mS = (S[0] + S[1] + S[2]) * (1.0f / 3.0f);
             float md[3];
@@ -541,20 +610,14 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
             for (int c = 0; c < 3; ++c) md[c] = S[c] - mS;
 #pragma unroll
             for (int k = 0; k <= K; ++k) {
-                float gd = 0.0f, Md = 0.0f, gm = 0.0f, Mm = 0.0f;
+                float gd = 0.0f, gm = 0.0f;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const float RB = R[c] * bs.B[k][c];
                     gd += RB * e[c];
-                    Md += RB * RB;
                     gm += bs.Bc[k][c] * md[c];
-                    Mm += bs.Bc[k][c] * bs.Bc[k][c];
                 }
-                const float at = fabsf(T[k]);
-                const float wis = (k > 0) ? L.is * rcp_pos(at + L.eps_irls) : 0.0f;
-                const float wnn = (T[k] > 0.0f) ? 0.0f : L.nn * rcp_pos(at + L.eps_nn);
-                g[3 + k] = L.data * gd - L.mo * w * gm - (wis + wnn) * T[k];
-                M[3 + k] = L.data * Md + L.mo * w * Mm + wis + wnn;
+                g[3 + k] = L.data * gd - L.mo * w * gm - w_unary(T[k], k, L) * T[k];
             }
             // reflectance sparsity stencil
             float wr[4];
@@ -564,7 +627,7 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     g[c] -= wr[d] * (r[c] - Ul[c * HN + li + off[d]]);
-                    M[c] += wr[d];
+                    M[c] = __fadd_rn(M[c], wr[d]);
                 }
             }
             // smoothness stencil
@@ -576,7 +639,7 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
                     const float tn = Ul[(3 + k) * HN + li + off[d]];
                     const float ws = L.sm * w_pair(T[k], tn, L.eps_irls);
                     g[3 + k] -= ws * (T[k] - tn);
-                    M[3 + k] += ws;
+                    M[3 + k] = __fadd_rn(M[3 + k], ws);
                 }
             }
             if (st.debug) {
@@ -588,9 +651,9 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
             } else {
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
+                    // the PCG iterations rebuild M from the unknowns, bit for bit, so it is not stored
                     const float mi = 1.0f / M[v];
                     const float z = g[v] * mi;
-                    a.minv[v * ps + i] = mi;
                     a.pA[v * ps + i] = z;   // x0 = 0 is not stored: iteration 1 starts from zero
                     acc += (double)g[v] * (double)z;
                 }
@@ -675,13 +738,14 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
     const int ht = (int)threadIdx.x;
     const int hrow = ht < HW ? 0 : (ht < 2 * HW ? TYW + 1 : 1 + ((ht - 2 * HW) >> 1));
     const int hcol = ht < 2 * HW ? ht % HW : (((ht - 2 * HW) & 1) ? HW - 1 : 0);
-    int t0, t1, ts;
-    tiles_of(a.ntiles, lc, t0, t1, ts);
+    const TileSet tset = tiles_of(a, lc);
     double acc[PV_N];
 #pragma unroll
     for (int v = 0; v < PV_N; ++v) acc[v] = 0.0;
-    for (int tile = t0; tile < t1; tile += ts) {
-        const int x0 = (tile % a.ntx) * TX, y0 = (tile / a.ntx) * TYW;
+    for (int tile = tset.c0; tile < tset.c1; ++tile) {
+        int tx, ty;
+        tile_xy(a, tset, tile, tx, ty);
+        const int x0 = tx * TX, y0 = ty * TYW;
         const int x = x0 + lx, y = y0 + ly;
         const bool own_in = x < W && y < H;
         const long long i = (long long)y * W + x;
@@ -698,26 +762,17 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
 #pragma unroll
             for (int v = 0; v < N; ++v) Ul[v * HN + li] = own_in ? uv[v] : 0.0f;
         }
-        // z and M^-1 of the own pixel, held through the stencil for the iteration's sums
-        float zk[N], mk[N];
+        // z of the own pixel, held through the stencil for the iteration's sums
+        float zk[N];
         if (dbg || first) {
             float pv[N];
 #pragma unroll
             for (int v = 0; v < N; ++v) pv[v] = pold[v * ps + io];
-            if (!dbg) {
 #pragma unroll
-                for (int v = 0; v < N; ++v) mk[v] = a.minv[v * ps + io];
-#pragma unroll
-                for (int v = 0; v < N; ++v) {
-                    zk[v] = pv[v];                     // z0 = p0
-                    acc[PV_RZ] += own_in ? (double)(zk[v] * rcp_pos(mk[v])) * (double)zk[v] : 0.0;
-                }
-            } else {
-#pragma unroll
-                for (int v = 0; v < N; ++v) zk[v] = mk[v] = 0.0f;
+            for (int v = 0; v < N; ++v) {
+                zk[v] = dbg ? 0.0f : pv[v];            // z0 = p0
+                Pl[v * HN + li] = own_in ? pv[v] : 0.0f;
             }
-#pragma unroll
-            for (int v = 0; v < N; ++v) Pl[v * HN + li] = own_in ? pv[v] : 0.0f;
         } else {
             float po[N], zv[N], qv[N], xv[N];
 #pragma unroll
@@ -726,7 +781,6 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
                 po[v] = pold[j];
                 zv[v] = zold[j];
                 qv[v] = qold[j];
-                mk[v] = a.minv[j];
                 xv[v] = X1 ? 0.0f : a.delta[j];
             }
 #pragma unroll
@@ -736,7 +790,6 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
                 const float p = fmaf(betaf, po[v], z);
                 xv[v] = (float)((double)xv[v] + alpha * (double)po[v]);
                 po[v] = p;
-                acc[PV_RZ] += own_in ? (double)(z * rcp_pos(mk[v])) * (double)z : 0.0;   // r = z / M^-1
                 Pl[v * HN + li] = own_in ? p : 0.0f;
             }
             if (own_in) {
@@ -793,19 +846,14 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
         __syncthreads();
         if (own_in) {
             const bool hv[4] = {x + 1 < W, y + 1 < H, x > 0, y > 0};
-            float p[N], q[N], T[K + 1], R[3], S[3];
+            float p[N], q[N], T[K + 1], R[3], S[3], rv[3];
 #pragma unroll
             for (int v = 0; v < N; ++v) p[v] = Pl[v * HN + li];
 #pragma unroll
             for (int k = 0; k <= K; ++k) T[k] = Ul[(3 + k) * HN + li];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                R[c] = expf(Ul[c * HN + li]);
-                float sum = 0.0f;
-#pragma unroll
-                for (int k = 0; k <= K; ++k) sum += bs.B[k][c] * T[k];
-                S[c] = sum;
-            }
+            for (int c = 0; c < 3; ++c) rv[c] = Ul[c * HN + li];
+            refl_shading<K>(rv, T, bs, R, S);
             // data term block
             float ac[3];
 #pragma unroll
@@ -820,6 +868,9 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
             for (int c = 0; c < 3; ++c) q[c] = L.data * R[c] * S[c] * ac[c] + (L.cl + L.rc * gs) * p[c];
             // monochrome block and unary layer terms
             const float w = a.wsr[i];
+            // Jacobi diagonal, rebuilt as the build formed it (no M^-1 plane is read)
+            float M[N];
+            diag_unary<K>(R, S, T, w, gs, bs, L, M);
             float m[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -836,10 +887,7 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
                     sd += R[c] * bs.B[k][c] * ac[c];
                     sm += bs.Bc[k][c] * m[c];
                 }
-                const float at = fabsf(T[k]);
-                const float wis = (k > 0) ? L.is * rcp_pos(at + L.eps_irls) : 0.0f;
-                const float wnn = (T[k] > 0.0f) ? 0.0f : L.nn * rcp_pos(at + L.eps_nn);
-                q[3 + k] = L.data * sd + L.mo * w * sm + (wis + wnn) * p[3 + k];
+                q[3 + k] = L.data * sd + L.mo * w * sm + w_unary(T[k], k, L) * p[3 + k];
             }
             // reflectance sparsity stencil
             float wr[4];
@@ -847,7 +895,10 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
 #pragma unroll
             for (int d = 0; d < 4; ++d)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) q[c] += wr[d] * (p[c] - Pl[c * HN + li + off[d]]);
+                for (int c = 0; c < 3; ++c) {
+                    q[c] += wr[d] * (p[c] - Pl[c * HN + li + off[d]]);
+                    M[c] = __fadd_rn(M[c], wr[d]);
+                }
             // smoothness stencil (one layer at a time: unrolling it makes the
             // compiler hoist every layer's LDS reads and double the registers)
 #pragma unroll 1
@@ -857,6 +908,7 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
                     if (!hv[d]) continue;
                     const float ws = L.sm * w_pair(T[k], Ul[(3 + k) * HN + li + off[d]], L.eps_irls);
                     q[3 + k] += ws * (p[3 + k] - Pl[(3 + k) * HN + li + off[d]]);
+                    M[3 + k] = __fadd_rn(M[3 + k], ws);
                 }
             }
             if (dbg) {
@@ -865,11 +917,12 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
             } else {
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
-                    const float mq = q[v] * mk[v];   // M^-1 q, what the next iteration reads
+                    const float mq = q[v] * (1.0f / M[v]);   // M^-1 q, what the next iteration reads
                     qcur[v * ps + i] = mq;
                     acc[PV_PQ] += (double)p[v] * (double)q[v];
                     acc[PV_QZ] += (double)q[v] * (double)zk[v];
                     acc[PV_QMQ] += (double)q[v] * (double)mq;
+                    acc[PV_RZ] += (double)(zk[v] * M[v]) * (double)zk[v];   // r = M z
                 }
             }
         }
@@ -936,8 +989,7 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
     // this workgroup's tiles (XCD-aware)
-    int t0, t1, ts;
-    tiles_of(a.ntiles, lc, t0, t1, ts);
+    const TileSet tset = tiles_of(a, lc);
     const int wl = (int)threadIdx.x & 63, wg_in = wl / (3 * K);
     const int grp = ((int)threadIdx.x >> 6) * GPW + wg_in, lane = wl % (3 * K);
     const bool owner = wg_in < GPW;
@@ -952,8 +1004,9 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
         for (int c = 0; c < 3; ++c) B64[k][c] = st.refine ? a.b64[3 * k + c] : 0.0;
     const int rows = TYW * a.ppt;
     const int tile_px = TX * rows;
-    for (int tile = t0; tile < t1; tile += ts) {
-        const int tx = tile % a.ntx, ty = tile / a.ntx;
+    for (int tile = tset.c0; tile < tset.c1; ++tile) {
+        int tx, ty;
+        tile_xy(a, tset, tile, tx, ty);
         for (int base = 0; base < tile_px; base += BS_BATCH) {
             // stage: every thread owns one pixel of the batch
             const int lp = base + threadIdx.x;

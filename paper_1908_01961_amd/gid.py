@@ -111,6 +111,8 @@ SIGNATURES = [
     ("gid_set_warmstart", c_int32, [c_void_p, c_void_p]),
     ("gid_cluster_frame", c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,
                                     POINTER(c_double), POINTER(c_double), POINTER(c_int32)]),
+    ("gid_resynthesize", c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p]),
     ("gid_status_string", ctypes.c_char_p, [c_int32]),
     ("gid_last_error", ctypes.c_char_p, [c_void_p]),
 ]
@@ -195,6 +197,30 @@ def cluster_frame(frame, k_max: int = 10, merge_dist: float = 0.2, stream=None):
         raise GidError(st, "gid_cluster_frame")
     n = k.value
     return ids, cols[:3 * n].reshape(n, 3).copy(), cen[:3 * n].reshape(n, 3).copy()
+
+
+def resynthesize(layers, b_new, gain=None, ids=None, refl_scale=None, out=None, stream=None):
+    """Recombine layers ((K+4, H, W) float32 CUDA tensor, R first) with edited base
+    colours b_new (K, 3), per-layer gains (K,) and a per-cluster reflectance scale
+    (K, 3) applied through ids ((H, W) uint8 CUDA tensor); returns (3, H, W)."""
+    import torch
+    lib = load_library()
+    n, H, W = (int(v) for v in layers.shape)
+    K = n - 4
+    lp = _ptr(layers, torch.float32, (n, H, W), "layers")
+    out = torch.empty((3, H, W), dtype=torch.float32, device=layers.device) if out is None else out
+    op = _ptr(out, torch.float32, (3, H, W), "out")
+    b = np.ascontiguousarray(np.asarray(b_new, np.float64).reshape(-1))
+    g = None if gain is None else np.ascontiguousarray(np.asarray(gain, np.float32).reshape(-1))
+    sc = None if refl_scale is None else np.ascontiguousarray(np.asarray(refl_scale, np.float32).reshape(-1))
+    ip = _ptr(ids, torch.uint8, (H, W), "ids") if ids is not None else None
+    sp = c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    st = lib.gid_resynthesize(lp, W, H, K, b.ctypes.data_as(POINTER(c_double)),
+                              None if g is None else c_void_p(g.ctypes.data),
+                              ip, None if sc is None else c_void_p(sc.ctypes.data), sp, op)
+    if st != GID_OK:
+        raise GidError(st, "gid_resynthesize")
+    return out
 
 
 class Solver:
