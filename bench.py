@@ -10,10 +10,13 @@ step then decomposes frames 1..F-1 from that checkpoint.
 
   plain    every frame warm-started from the previous result, fixed 3 x 8.
   learned  the network's prediction from the previous result, judged against
-           it by the energy, then outer iterations until the frame's energy is
-           at or below the plain method's final energy on that frame times
-           (1 + 1e-4), up to 2 G iterations (device-side stop, no host trips).
-           Network inference, the judge and every energy evaluation are timed.
+           it by the energy, then outer iterations (P or fewer PCG iterations
+           each: 8, 6 and 4 are tried) until the frame's energy is at or below
+           the plain method's final energy on that frame times (1 + 1e-4), up to
+           twice the plain schedule's PCG iterations (device-side stop, no host
+           trips).  Network inference, the judge and every energy evaluation
+           are timed.  The same continuation from the plain start (no network)
+           is reported as the control.
 
 The learned run counts as matched when every frame meets its target.  `value`
 is the throughput at the fixed final energy: the learned path's when matched
@@ -63,10 +66,11 @@ def method_bytes(n: int, tau: int, G: int, P: int) -> dict:
 def impl_bytes(n: int, tau: int, P: int) -> float:
     """Bytes per pixel the implementation's PCG launches move on average: with
     the vectors carried in preconditioned form an iteration i > 1 reads u, z,
-    M^-1 q, p, x and M^-1 (n planes each), the soft-Retinex weight and the
-    temporal pair count, and writes x, z, p and M^-1 q; iteration 1 starts x
-    from zero; iteration 0 reads u, p0 and M^-1 and writes M^-1 q."""
-    its = [4 * n + 1 + tau, 8 * n + 1 + tau] + [10 * n + 1 + tau] * max(0, P - 2)
+    M^-1 q, p and x (n planes each), the soft-Retinex weight and the temporal
+    pair count, and writes x, z, p and M^-1 q (the Jacobi diagonal is rebuilt
+    from u); iteration 1 starts x from zero; iteration 0 reads u and p0 and
+    writes M^-1 q."""
+    its = [3 * n + 1 + tau, 7 * n + 1 + tau] + [9 * n + 1 + tau] * max(0, P - 2)
     return 4.0 * sum(its[:P]) / max(P, 1)
 
 
@@ -124,9 +128,9 @@ class Video:
         s.close()
         self.px = (self.F - 1) * self.W * self.H
 
-    def solver(self, G_=None):
+    def solver(self, G_=None, P_=None):
         import paper_1908_01961_amd as G
-        return G.Solver(self.W, self.H, G.default_params(self.K, gn_iters=G_ or self.G, pcg_iters=self.P,
+        return G.Solver(self.W, self.H, G.default_params(self.K, gn_iters=G_ or self.G, pcg_iters=P_ or self.P,
                                                          temporal=1, refine_mode="every", record_energy=0,
                                                          use_graph=1))
 
@@ -186,7 +190,7 @@ def frame_roofline(video, sec_per_frame):
                 algorithmic_bytes_per_frame=mb)
 
 
-def train_network(video, train_frames):
+def train_network(video, train_frames, w):
     import paper_1908_01961_amd as G
     from paper_1908_01961_amd import warmstart as WSP
     W_, H_, K = video.W, video.H, video.K
@@ -195,7 +199,9 @@ def train_network(video, train_frames):
     while (W_ // f) * (H_ // f) > 80000:
         f += 1
     tw, th = max(64, W_ // f), max(32, H_ // f)       # the workload's aspect, about 77k pixels
-    store = WSP.make_training_set(K, tw, th, train_frames, 41, video.G, video.P, 10000)
+    # training scenes drawn from the workload's own recipe (indirect amplitude, edge sampling)
+    store = WSP.make_training_set(K, tw, th, train_frames, 41, video.G, video.P, 10000, amp=w["amp"],
+                                  supersample=w["supersample"])
     net_t = G.Net(K, tw, th)
     net_t.set_params(WSP.init_params(K, 1))
     hist = WSP.train(net_t, store, epochs=4, lr=1e-3)
@@ -226,33 +232,52 @@ def bench_video(args, clip, workload, learned=True):
                frame_roofline=frame_roofline(video, t_plain / (video.F - 1)), E_plain=E_plain)
     if not learned:
         return res
-    net, train = train_network(video, args.train_frames)
-    max_gn = 2 * w["G"]
+    net, train = train_network(video, args.train_frames, w)
     targets = E_plain * (1.0 + 1e-4)
-    sl = video.solver(max_gn)
-    sl.set_warmstart(net)
-    t_l, last = video.timed(sl, args.steps, args.warmup, targets, max_gn)
-    E_l = np.array([e for e, _, _ in last])
-    gn = np.array([g for _, g, _ in last])
-    taken = int(sum(1 for _, _, k in last if k == 1))
-    sl.close()
+
+    def run(Pl, with_net, steps, warmup):
+        # at most twice the plain schedule's PCG iterations per frame
+        max_gn = -(-2 * w["G"] * w["P"] // Pl)
+        sl = video.solver(max_gn, Pl)
+        if with_net:
+            sl.set_warmstart(net)
+        t, last = video.timed(sl, steps, warmup, targets, max_gn)
+        sl.close()
+        E_l = np.array([e for e, _, _ in last])
+        gn = np.array([g for _, g, _ in last])
+        ex = E_l / E_plain - 1.0
+        d = dict(pcg_iters=Pl, max_gn=max_gn, mpx_s=round(video.px / t / 1e6, 2),
+                 frames_s=round((video.F - 1) / t, 1), gn_mean=round(float(gn.mean()), 3), gn_max=int(gn.max()),
+                 gn_histogram={int(g): int((gn == g).sum()) for g in np.unique(gn)},
+                 energy_excess_max=float(ex.max()), energy_excess_median=float(np.median(ex)),
+                 matched=bool(np.all(E_l <= targets)))
+        if with_net:
+            d["learned_start_taken"] = f"{int(sum(1 for _, _, k in last if k == 1))}/{video.F - 1}"
+        return t, d
+
+    # the continuation with the network's start and a reduced PCG count per outer
+    # iteration (G x P is the plain method's reference schedule); the fastest
+    # matched candidate is timed in full, and the same schedule from the plain
+    # start (no network) is its control
+    cands = []
+    for Pl in sorted({w["P"], 6, 4}, reverse=True):
+        t, d = run(Pl, True, 2, 1)
+        cands.append((t, d))
+        log(f"learned, {Pl} PCG per outer iteration: {d}")
+    ok = [(t, d) for t, d in cands if d["matched"]]
+    best = min(ok, key=lambda td: td[0]) if ok else min(cands, key=lambda td: td[0])
+    t_l, dl = run(best[1]["pcg_iters"], True, args.steps, args.warmup)
+    t_c, dc = run(best[1]["pcg_iters"], False, 2, 1)
     net.close()
-    matched = bool(np.all(E_l <= targets))
-    l_mpx = video.px / t_l / 1e6
-    ex = E_l / E_plain - 1.0
-    log(f"learned + continuation: {t_l * 1e3:.1f} ms per pass, {l_mpx:.1f} Mpx/s, outer iterations "
-        f"mean {gn.mean():.2f} (max {gn.max()}), matched {matched}")
+    matched = dl["matched"]
+    log(f"learned + continuation: {t_l * 1e3:.1f} ms per pass, {dl['mpx_s']:.1f} Mpx/s, outer iterations "
+        f"mean {dl['gn_mean']:.2f} (max {dl['gn_max']}), matched {matched}; plain start, same continuation: "
+        f"{dc['mpx_s']:.1f} Mpx/s, matched {dc['matched']}")
     res["learned"] = dict(
         frames_timed=video.F - 1, criterion="E_learned[t] <= E_plain[t] * (1 + 1e-4) for every frame t >= 1",
         plain=dict(schedule=f"{w['G']}x{w['P']}", mpx_s=round(plain_mpx, 2),
                    frames_s=round((video.F - 1) / t_plain, 1)),
-        learned=dict(mpx_s=round(l_mpx, 2), frames_s=round((video.F - 1) / t_l, 1), max_gn=max_gn,
-                     gn_mean=round(float(gn.mean()), 3), gn_max=int(gn.max()),
-                     gn_histogram={int(g): int((gn == g).sum()) for g in np.unique(gn)},
-                     learned_start_taken=f"{taken}/{video.F - 1}",
-                     energy_excess_max=float(ex.max()), energy_excess_median=float(np.median(ex)),
-                     matched=matched),
-        train=train,
+        learned=dl, candidates=[d for _, d in cands], control_plain_start_same_continuation=dc, train=train,
         speedup_at_matched_energy=round(t_plain / t_l, 3) if matched else None)
     res["t_learned"] = t_l
     return res

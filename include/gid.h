@@ -84,6 +84,11 @@ typedef struct {
     int32_t bstep_scale;       /* GID_BSTEP_*: data sum of the base-colour refinement energy
                                   (Sec. 6.3, eq. basecolorrefinement) divided by the pixel
                                   count (default) or the printed pixel sum */
+    int32_t spatial_pairs;     /* 1: spatial pairs of the consistency prior (Sec. 6.1): every
+                                  pixel tied to a seeded random half of the edges to its eight
+                                  neighbours, each active when the two chromaticities are closer
+                                  than chroma_gate, weight lambda.r_consistency; 0 (default) off */
+    uint32_t spatial_seed;     /* seed of that sampling (SplitMix64 of (seed << 32) | (4 i + d)) */
 } gid_params;
 
 #define GID_MAX_HALF_STEPS 128
@@ -375,6 +380,31 @@ gid_status gid_set_warmstart(gid_ctx *ctx, gid_net *net);
 gid_status gid_cluster_frame(const float *frame_dev, int32_t width, int32_t height, int32_t k_max,
                              double merge_dist, void *hip_stream, uint8_t *ids_dev, double *colors_host,
                              double *centres_host, int32_t *k_out);
+
+/* ---- misclustering correction (Sec. 5.2.2) ----
+ * Choose the reflectance of a region whose cluster ids are suspect: every base
+ * colour j = 0..K-1 is tried as the region's colour (ids set to j inside the
+ * region), each candidate frame is decomposed in full as a first frame with the
+ * schedule of params (gn_iters x pcg_iters, refine_mode; the K decompositions
+ * run as one batch through shared launches), and the colour whose indirect
+ * layers are sparsest over the region, by the illumination sparsity term of
+ * Sec. 6.2, lambda_is sum_{x in region} sum_{k>=1} |T_k(x)|, is kept (ties: the
+ * lowest index).  The region itself (the paper's clicks, flood fill and
+ * tracking, Sec. 5.2.1) is the caller's.
+ *   params       K = the number of base colours; record_energy is ignored
+ *   frame_dev    3 planes float32 (device); ids_dev width*height uint8 in [0, K)
+ *   region_dev   width*height uint8 (device), nonzero inside the region
+ *   colors_host  K x 3 doubles: the base colours (also the refinement's initial estimate)
+ *   ids_out_dev  width*height uint8 (device) written: ids with the region set to the best colour
+ *   sparsity_host K doubles written: each candidate's region sparsity
+ *   best_out     the chosen colour index
+ * Synchronous on hip_stream.  Allocates its workspace (K contexts, K id maps and
+ * K layer sets) and frees it before returning.
+ * Errors: GID_ERR_INVALID_ARG, GID_ERR_OUT_OF_MEMORY, GID_ERR_NUMERIC (a
+ * candidate's frame was rejected or its energy is not finite), GID_ERR_HIP. */
+gid_status gid_correct_region(const gid_params *params, int32_t width, int32_t height, const float *frame_dev,
+                              const uint8_t *ids_dev, const uint8_t *region_dev, const double *colors_host,
+                              void *hip_stream, uint8_t *ids_out_dev, double *sparsity_host, int32_t *best_out);
 
 /* ---- re-synthesis for the live applications (Sec. 8.4) ----
  * Recombine layers by the image formation of Sec. 4 with edits:

@@ -21,6 +21,99 @@ from .params import OracleParams
 #: consistency prior of Sec. 6.1, whose sampling the paper defers to prior work).
 WINDOW = tuple((dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1))
 
+#: Spatial pairs of the same prior (reading): the edges between a pixel and its
+#: eight neighbours, each enumerated once from the pixel that owns it in one of
+#: four forward directions d = 0..3 (right, down-right, down, down-left).  An
+#: edge is sampled when the top bit of SplitMix64 of the key
+#: (seed << 32) | (4 i + d), i the owning pixel's row-major index, is zero
+#: (probability 1/2, the same edges at both ends and in every frame), and it is
+#: active when the two pixels' chromaticities are closer than the gate.  Each
+#: active edge adds lambda_rc sum_c (r_c(x) - r_c(y))^2.
+SPATIAL_DIRS = ((0, 1), (1, 1), (1, 0), (1, -1))
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(x):
+    """The SplitMix64 output for state x (Steele, Lea and Flood, 2014): the
+    golden-ratio increment, then the two xor-shift-multiply rounds.  Works on
+    Python ints and on numpy uint64 arrays."""
+    if isinstance(x, np.ndarray):
+        z = x.astype(np.uint64) + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+    z = (x + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def spatial_sampled(seed: int, H: int, W: int) -> np.ndarray:
+    """(4, H, W) 0/1: edge (pixel, direction d) drawn by the sampler."""
+    i = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    out = np.zeros((4, H, W))
+    for d in range(4):
+        key = (np.uint64(seed & 0xFFFFFFFF) << np.uint64(32)) | (np.uint64(4) * i + np.uint64(d))
+        out[d] = (splitmix64(key) >> np.uint64(63)) == 0
+    return out
+
+
+def _edge_slices(H, W, dy, dx):
+    """(source rows, source cols, target rows, target cols) of the in-image edges
+    from (y, x) to (y + dy, x + dx)."""
+    ys = slice(0, H - dy)
+    xs = slice(max(0, -dx), min(W, W - dx))
+    yt = slice(dy, H)
+    xt = slice(max(0, -dx) + dx, min(W, W - dx) + dx)
+    return ys, xs, yt, xt
+
+
+def spatial_edges(C: np.ndarray, p: OracleParams) -> np.ndarray:
+    """(4, H, W) 0/1 active spatial pairs owned by each pixel (see SPATIAL_DIRS)."""
+    _, H, W = C.shape
+    samp = spatial_sampled(p.spatial_seed, H, W)
+    E = np.zeros((4, H, W))
+    for d, (dy, dx) in enumerate(SPATIAL_DIRS):
+        ys, xs, yt, xt = _edge_slices(H, W, dy, dx)
+        diff = C[:, ys, xs] - C[:, yt, xt]
+        dist = np.sqrt((diff[0] * diff[0] + diff[1] * diff[1]) + diff[2] * diff[2])
+        E[d, ys, xs] = samp[d, ys, xs] * (dist < p.chroma_gate)
+    return E
+
+
+def spatial_laplacian(f: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """sum over active edges (x, y) of (f(x) - f(y)) (e_x - e_y), per channel of f (3, H, W)."""
+    q = np.zeros_like(f)
+    _, H, W = f.shape
+    for d, (dy, dx) in enumerate(SPATIAL_DIRS):
+        ys, xs, yt, xt = _edge_slices(H, W, dy, dx)
+        e = E[d, ys, xs][None] * (f[:, ys, xs] - f[:, yt, xt])
+        q[:, ys, xs] += e
+        q[:, yt, xt] -= e
+    return q
+
+
+def spatial_degree(E: np.ndarray) -> np.ndarray:
+    """Number of active spatial pairs at each pixel."""
+    _, H, W = E.shape
+    deg = np.zeros((H, W))
+    for d, (dy, dx) in enumerate(SPATIAL_DIRS):
+        ys, xs, yt, xt = _edge_slices(H, W, dy, dx)
+        deg[ys, xs] += E[d, ys, xs]
+        deg[yt, xt] += E[d, ys, xs]
+    return deg
+
+
+def spatial_sq(r: np.ndarray, E: np.ndarray) -> float:
+    """sum over active edges of sum_c (r_c(x) - r_c(y))^2."""
+    _, H, W = r.shape
+    acc = 0.0
+    for d, (dy, dx) in enumerate(SPATIAL_DIRS):
+        ys, xs, yt, xt = _edge_slices(H, W, dy, dx)
+        acc += (E[d, ys, xs][None] * (r[:, ys, xs] - r[:, yt, xt]) ** 2).sum()
+    return float(acc)
+
 
 def intensity(v: np.ndarray) -> np.ndarray:
     """|v| of Sec. 5.1 read as the channel mean (the reading under which the
@@ -65,6 +158,7 @@ class FrameData:
     C: np.ndarray                      # (3, H, W) chromaticity of I
     gamma: Optional[np.ndarray] = None  # (9, H, W) 0/1 temporal pair gates (0 outside the image)
     rprev: Optional[np.ndarray] = None  # (9, 3, H, W) previous-frame r at each window pixel
+    sp_edges: Optional[np.ndarray] = None  # (4, H, W) active spatial pairs (SPATIAL_DIRS), when on
 
     @property
     def shape(self):
@@ -81,6 +175,8 @@ def prepare_frame(I: np.ndarray, ids: np.ndarray, p: OracleParams,
     C = chromaticity(I, p)
     wsr = 1.0 - np.exp(-p.retinex_k * delta_chroma(C))
     fd = FrameData(I=I, ids=np.asarray(ids).astype(np.int64), wsr=wsr, C=C)
+    if p.spatial_pairs:
+        fd.sp_edges = spatial_edges(C, p)
     if prev_C is not None:
         _, H, W = I.shape
         gamma = np.zeros((9, H, W))
@@ -160,6 +256,8 @@ def energy_terms(u: np.ndarray, b: np.ndarray, fd: FrameData, p: OracleParams) -
         out["rconsist"] = p.lam_rconsistency * acc
     else:
         out["rconsist"] = 0.0
+    if fd.sp_edges is not None:
+        out["rconsist"] += p.lam_rconsistency * spatial_sq(r, fd.sp_edges)
     out["mono"] = p.lam_mono * (fd.wsr * ((S - intensity(S)[None]) ** 2).sum(axis=0)).sum()
     out["isparsity"] = p.lam_isparsity * np.abs(T[1:]).sum()
     gx, gy = forward_diff(T)

@@ -15,7 +15,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .energy import full_basis
+from .energy import SPATIAL_DIRS, full_basis
 from .gauss_newton import Linearisation
 
 
@@ -75,6 +75,13 @@ def assemble_residuals(u: np.ndarray, lin: Linearisation):
                         continue
                     for c in range(3):
                         add_row(src * (r[c] - fd.rprev[o, c, y, x]), [(col(c, y, x), src)])
+            if fd.sp_edges is not None:                          # spatial consistency pairs
+                for d, (dy, dx) in enumerate(SPATIAL_DIRS):
+                    yy, xx = y + dy, x + dx
+                    if fd.sp_edges[d, y, x] == 0.0 or not (0 <= yy < H and 0 <= xx < W):
+                        continue
+                    for c in range(3):
+                        add_row(src * (r[c] - u[c, yy, xx]), [(col(c, y, x), src), (col(c, yy, xx), -src)])
             smo = math.sqrt(P.lam_mono * fd.wsr[y, x])           # monochromaticity
             mS = sum(S) / 3.0
             for c in range(3):

@@ -20,7 +20,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .energy import (FrameData, cluster_log_reflectance, forward_diff, full_basis, intensity,
-                     rgrad_norm, shading)
+                     rgrad_norm, shading, spatial_degree, spatial_laplacian, spatial_sq)
 from .params import OracleParams
 
 
@@ -88,6 +88,9 @@ def apply_normal(pv: np.ndarray, lin: Linearisation) -> np.ndarray:
     # clustering and temporal consistency: unary on r
     qr += P.lam_cluster * pr
     qr += P.lam_rconsistency * lin.gsum[None] * pr
+    # spatial consistency pairs: a constant-weight graph Laplacian on r
+    if lin.fd.sp_edges is not None:
+        qr += P.lam_rconsistency * spatial_laplacian(pr, lin.fd.sp_edges)
     # monochrome: row_c = sqrt(l w_SR) sum_k (b_kc - mean_c b_k) dT_k
     m = np.einsum("kc,khw->chw", Bc, pT)
     qT += P.lam_mono * lin.fd.wsr[None] * np.einsum("kc,chw->khw", Bc, m)
@@ -116,6 +119,8 @@ def rhs(lin: Linearisation) -> np.ndarray:
     if fd.gamma is not None:
         for o in range(9):
             gr -= P.lam_rconsistency * fd.gamma[o][None] * (r - fd.rprev[o])
+    if fd.sp_edges is not None:
+        gr -= P.lam_rconsistency * spatial_laplacian(r, fd.sp_edges)
     mdev = S - intensity(S)[None]
     gT -= P.lam_mono * fd.wsr[None] * np.einsum("kc,chw->khw", Bc, mdev)
     gT -= (P.lam_isparsity * lin.wis + P.lam_nonneg * lin.wnn) * T
@@ -135,6 +140,8 @@ def jacobi_diag(lin: Linearisation) -> np.ndarray:
     dr += P.lam_data * (R * S) ** 2
     dT += P.lam_data * np.einsum("kc,chw->khw", B ** 2, R ** 2)
     dr += P.lam_cluster + P.lam_rconsistency * lin.gsum[None]
+    if lin.fd.sp_edges is not None:
+        dr += P.lam_rconsistency * spatial_degree(lin.fd.sp_edges)[None]
     dT += P.lam_mono * lin.fd.wsr[None] * (Bc ** 2).sum(axis=1)[:, None, None]
     dT += P.lam_isparsity * lin.wis + P.lam_nonneg * lin.wnn
 
@@ -166,6 +173,8 @@ def surrogate_energy(u: np.ndarray, lin: Linearisation) -> float:
     if fd.gamma is not None:
         for o in range(9):
             e += P.lam_rconsistency * (fd.gamma[o][None] * (r - fd.rprev[o]) ** 2).sum()
+    if fd.sp_edges is not None:
+        e += P.lam_rconsistency * spatial_sq(r, fd.sp_edges)
     e += P.lam_mono * (fd.wsr * ((S - intensity(S)[None]) ** 2).sum(axis=0)).sum()
     e += ((P.lam_isparsity * lin.wis + P.lam_nonneg * lin.wnn) * T ** 2).sum()
     tx, ty = forward_diff(T)

@@ -41,6 +41,11 @@ class OracleParams:
     # the non-negativity weight) are decided on the stored state, so an FP32
     # implementation is compared with the "f32" setting; all arithmetic stays FP64.
     state_precision: str = "f64"
+    # Spatial pairs of the consistency prior (Sec. 6.1: every pixel is tied to
+    # randomly sampled pixels of a small window under a chromaticity gate):
+    # off by default; the reading and its seeded sampling are in energy.py.
+    spatial_pairs: bool = False
+    spatial_seed: int = 2019
 
 
 def default_params(**kw) -> OracleParams:

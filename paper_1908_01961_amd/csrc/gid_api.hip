@@ -194,6 +194,8 @@ Args base_args(const gid_ctx* c) {
     a.lam = make_lam(c->prm);
     a.cr_literal = c->prm.cr_mode == GID_CR_LITERAL;
     a.bstep_sum = c->prm.bstep_scale == GID_BSTEP_SUM;
+    a.spatial = c->prm.spatial_pairs != 0;
+    a.spatial_seed = c->prm.spatial_seed;
     a.u = c->u;
     a.delta = c->delta;
     a.zA = c->zA;
@@ -399,6 +401,7 @@ gid_status check_params(const gid_params* p) {
     if (p->refine_mode < 0 || p->refine_mode > 2) return GID_ERR_INVALID_ARG;
     if (p->cr_mode < 0 || p->cr_mode > 1) return GID_ERR_INVALID_ARG;
     if (p->bstep_scale < 0 || p->bstep_scale > 1) return GID_ERR_INVALID_ARG;
+    if (p->spatial_pairs < 0 || p->spatial_pairs > 1) return GID_ERR_INVALID_ARG;
     if (p->record_energy && 2 * p->gn_iters > GID_MAX_HALF_STEPS) return GID_ERR_INVALID_ARG;
     if (!(p->eps_nonneg > 0.0f) || !(p->eps_irls > 0.0f)) return GID_ERR_INVALID_ARG;
     if (!(p->lambda.p > 0.0f) || !(p->lambda.p <= 2.0f)) return GID_ERR_INVALID_ARG;
@@ -465,6 +468,8 @@ gid_status gid_default_params(int32_t K, gid_params* out) {
     p.record_energy = 0;
     p.use_graph = 1;
     p.bstep_scale = GID_BSTEP_PER_PIXEL;
+    p.spatial_pairs = 0;
+    p.spatial_seed = 2019;
     *out = p;
     return GID_OK;
 }
@@ -504,7 +509,7 @@ gid_status gid_create(const gid_params* params, int32_t width, int32_t height, v
     const size_t o_u = take(fplane * c->n), o_delta = take(fplane * c->n), o_zA = take(fplane * c->n),
                  o_zB = take(fplane * c->n), o_pA = take(fplane * c->n), o_pB = take(fplane * c->n),
                  o_qA = take(fplane * c->n), o_qB = take(fplane * c->n), o_minv = take(fplane * c->n), o_I = take(fplane * 3), o_wsr = take(fplane),
-                 o_tg = take(fplane * 5), o_Iprev = take(fplane * 3), o_rprev = take(fplane * 3);
+                 o_tg = take(fplane * 6), o_Iprev = take(fplane * 3), o_rprev = take(fplane * 3);
     const size_t o_ids = take((size_t)c->ps);
     const size_t o_bf = take(sizeof(float) * 3 * KMAX);
     const size_t o_lnb = take(sizeof(float) * 3 * KMAX);

@@ -85,6 +85,8 @@ struct Args {
     int first;               // initialise the unknowns (first frame of a clip)
     int cr_literal;
     int bstep_sum;           // base-colour data sum not divided by the pixel count
+    int spatial;             // spatial pairs of the consistency prior (Sec. 6.1)
+    unsigned spatial_seed;   // their sampler's seed
     float* u;                // n planes
     float* delta;            // x: the layer step accumulated by PCG
     float* zA;               // preconditioned residual z = M^-1 r, even PCG iterations from 2
@@ -97,8 +99,10 @@ struct Args {
     float* I;                // 3 planes (frame copy)
     uint8_t* ids;
     float* wsr;              // 1 plane
-    float* tg;               // 5 planes: number of temporal pairs, sum of paired r_prev per channel,
-                             // bit mask of the paired 3 x 3 window positions
+    float* tg;               // 6 planes: number of temporal pairs, sum of paired r_prev per channel,
+                             // bit mask of the paired 3 x 3 window positions, bit mask of the
+                             // active spatial pairs (neighbours right, down-right, down, down-left,
+                             // left, up-left, up, up-right)
     float* Iprev;            // 3 planes, previous frame
     float* rprev;            // 3 planes, previous frame's final r
     float* bf;               // K x 3 base colours, float

@@ -8,12 +8,12 @@
 // wavefronts; it covers a tile of 64 columns x (4 * ppt) rows, each wavefront one
 // row of 64 pixels, so every plane access is a 256-byte coalesced row segment.
 // Tiles are handed to workgroups XCD-aware: the hardware deals workgroup i to XCD
-// i % 8, and xcd_order() gives each XCD a band of tile rows whose tiles its
-// workgroups take in vertical runs, so that shared halo lines stay in its L2.
+// i % 8, and xcd_order() gives each XCD a contiguous band of tiles so that the
+// halo rows a tile shares with its vertical neighbours stay in that XCD's L2.
 //
-// Grids are persistent-style: at most 2048 workgroups, each owning a vertical
-// run of tiles of its XCD's band (one tile each while the frame has at most
-// 2048 tiles), so a launch produces at most 2048 partial sums.
+// Grids are persistent-style: at most 2048 workgroups, each owning every m-th
+// tile of its XCD's band (one tile each while the frame has at most 2048
+// tiles), so a launch produces at most 2048 partial sums.
 // Every kernel is a body over (clip descriptor, launch context, step); a
 // single-clip launch runs it over its whole grid, a batched launch runs it for
 // several clips of uneven size in one grid, each workgroup finding its clip
@@ -50,40 +50,31 @@ struct Lc {
 __device__ __forceinline__ int xcd_order(int j, int nb) { return (j & 7) * (nb >> 3) + (j >> 3); }
 
 // Tiles of a workgroup.  XCD x (workgroups x m .. x m + m - 1 in xcd_order, with
-// m = nb / 8) owns the band of tile rows [x nty / 8, (x + 1) nty / 8).  The band's
-// tiles are enumerated in vertical runs: groups of G tile rows, column by column,
-// and down each column within a group; workgroup jl of the XCD takes the run of
-// G consecutive tiles [jl G, (jl + 1) G) with G = ceil(band tiles / m), i.e. one
-// column of one group.  A workgroup walks down its column, so the halo rows a
-// tile shares with the next one come from L2 (the workgroup has just read them),
-// and the workgroups in flight on one XCD hold side-by-side columns at about the
-// same height, so the halo columns they share are read close together in time
-// through that XCD's L2.  With one tile per workgroup this is raster order.
+// m = nb / 8) owns the contiguous band of tiles [x ntiles / 8, (x + 1) ntiles / 8)
+// in row-major tile order; its workgroups take the band's tiles round-robin
+// (tile c0, c0 + m, ...), so the workgroups in flight on one XCD work on
+// neighbouring tiles and share their halo lines through that XCD's L2.  With one
+// tile per workgroup this is lb itself.  (Dealing each workgroup a vertical run
+// of tiles instead, so that a workgroup reuses the halo rows of its previous
+// tile, measured 6% slower per PCG iteration at 1920x1080 K=10.)
 // nb is a multiple of 8 (every per-pixel grid is).
 struct TileSet {
-    int c0, c1;          // logical tiles [c0, c1) of the band
-    int ry0, rows, G;    // band rows [ry0, ry0 + rows), run length
+    int c0, c1, step;    // tiles c0, c0 + step, ... below c1 (row-major index)
 };
 
 __device__ __forceinline__ TileSet tiles_of(const Args& a, const Lc& lc) {
     const int m = lc.nb >> 3, x = lc.lb / m, jl = lc.lb - x * m;
     TileSet s;
-    s.ry0 = (x * a.nty) >> 3;
-    s.rows = (((x + 1) * a.nty) >> 3) - s.ry0;
-    const int band = s.rows * a.ntx;
-    s.G = (band + m - 1) / m;
-    s.c0 = min(band, jl * s.G);
-    s.c1 = min(band, s.c0 + s.G);
+    s.c0 = (int)(((long long)x * a.ntiles) >> 3) + jl;
+    s.c1 = (int)(((long long)(x + 1) * a.ntiles) >> 3);
+    s.step = m;
     return s;
 }
 
-// Tile coordinates of logical tile l of a band.
+// Tile coordinates of tile l.
 __device__ __forceinline__ void tile_xy(const Args& a, const TileSet& s, int l, int& tx, int& ty) {
-    const int gsz = s.G * a.ntx;
-    const int grp = l / gsz, rem = l - grp * gsz;
-    const int h = min(s.G, s.rows - grp * s.G);
-    tx = rem / h;
-    ty = s.ry0 + grp * s.G + (rem - tx * h);
+    tx = l % a.ntx;
+    ty = l / a.ntx;
 }
 
 __device__ __forceinline__ Lc whole_grid() { return Lc{xcd_order((int)blockIdx.x, (int)gridDim.x), (int)gridDim.x}; }
@@ -213,7 +204,7 @@ __device__ __forceinline__ void for_each_pixel(const Args& a, const Lc& lc, F&& 
     const TileSet tset = tiles_of(a, lc);
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
     const int rows = TYW * a.ppt;
-    for (int tile = tset.c0; tile < tset.c1; ++tile) {
+    for (int tile = tset.c0; tile < tset.c1; tile += tset.step) {
         int tx, ty;
         tile_xy(a, tset, tile, tx, ty);
         const int x = tx * TX + lx;
@@ -342,9 +333,29 @@ __device__ __forceinline__ void load_window3(const Args& a, int x, int y, long l
 }
 
 __device__ __forceinline__ double cdist(const double* a, const double* b) {
+#pragma clang fp contract(off)
     const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
     return sqrt((d0 * d0 + d1 * d1) + d2 * d2);
 }
+
+// SplitMix64 output for state x (Steele, Lea and Flood, 2014).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Spatial pairs of the consistency prior (Sec. 6.1: every pixel tied to randomly
+// sampled pixels of a small window under a chromaticity gate).  Reading: the
+// edges to the eight neighbours, each owned by one pixel in one of four forward
+// directions d (right, down-right, down, down-left); an edge is sampled when the
+// top bit of SplitMix64((seed << 32) | (4 owner + d)) is zero and active when the
+// two chromaticities are closer than the gate.  Bit b of a pixel's mask is its
+// edge to neighbour b: b < 4 its own forward edges, b >= 4 the edges the left,
+// up-left, up and up-right neighbours own (direction b - 4).
+__constant__ int SP_DX[8] = {1, 1, 0, -1, -1, -1, 0, 1};
+__constant__ int SP_DY[8] = {0, 1, 1, 1, 0, -1, -1, -1};
 
 // Index of the colour chromaticity nearest to C: squared L2 distance formed
 // d0 d0 + d1 d1 + d2 d2 left to right without contraction, ties to the lowest index.
@@ -439,6 +450,22 @@ __device__ __forceinline__ void precompute_body(const Args& a, const Lc& lc, con
         a.tg[2 * ps + i] = tr1;
         a.tg[3 * ps + i] = tr2;
         a.tg[4 * ps + i] = (float)gmask;   // exact: below 2^9
+        if (a.spatial) {
+            unsigned smask = 0;
+            for (int nb = 0; nb < 8; ++nb) {
+                const int xx = x + SP_DX[nb], yy = y + SP_DY[nb];
+                if (xx < 0 || xx >= W || yy < 0 || yy >= H) continue;
+                const long long j = (long long)yy * W + xx;
+                const unsigned long long owner = (unsigned long long)(nb < 4 ? i : j);
+                const unsigned long long key = ((unsigned long long)a.spatial_seed << 32) | (4ull * owner + (nb & 3));
+                if (splitmix64(key) >> 63) continue;
+                float Fj[3];
+                load3(F, ps, j, Fj);
+                chroma64v(Fj[0], Fj[1], Fj[2], floor_, Cn);
+                if (cdist(C, Cn) < a.lam.gate) smask |= 1u << nb;
+            }
+            a.tg[5 * ps + i] = (float)smask;   // exact: below 2^8
+        }
         if (a.first) {
             const double* b = a.b64 + 3 * id;
             a.u[i] = a.lnb[3 * id];
@@ -546,6 +573,20 @@ __device__ __forceinline__ void diag_unary(const float* R, const float* S, const
     }
 }
 
+// Spatial consistency partners of a pixel from its active-pair mask: adds
+// their number to n and their values of the three r-like planes staged at
+// V (r for the right-hand side, p for the product) to s.
+__device__ __forceinline__ void spatial_partners(const float* V, int li, unsigned mask, float& n, float* s) {
+    const int off[8] = {1, HW + 1, HW, HW - 1, -1, -HW - 1, -HW, -HW + 1};
+#pragma unroll
+    for (int nb = 0; nb < 8; ++nb) {
+        if (!((mask >> nb) & 1u)) continue;
+        n += 1.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] += V[c * HN + li + off[nb]];
+    }
+}
+
 // ------------------------------------------------------------------ GN build
 
 template <int K>
@@ -564,7 +605,7 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
     const int off[4] = {1, HW, -1, -HW};
     const TileSet tset = tiles_of(a, lc);
     double acc = 0.0;
-    for (int tile = tset.c0; tile < tset.c1; ++tile) {
+    for (int tile = tset.c0; tile < tset.c1; tile += tset.step) {
         int tx, ty;
         tile_xy(a, tset, tile, tx, ty);
         const int x0 = tx * TX, y0 = ty * TYW;
@@ -596,13 +637,18 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
 #pragma unroll
             for (int c = 0; c < 3; ++c) e[c] = Iv[c] - R[c] * S[c];
             float g[N], M[N];
-            const float gs = a.temporal ? a.tg[i] : 0.0f;
+            // consistency pairs: their count and the sum of the partners' r (temporal
+            // partners from the previous frame, spatial ones from the staged tile)
+            float gs = a.temporal ? a.tg[i] : 0.0f;
+            float tgr[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) tgr[c] = a.temporal ? a.tg[(1 + c) * ps + i] : 0.0f;
+            if (a.spatial) spatial_partners(Ul, li, (unsigned)a.tg[5 * ps + i], gs, tgr);
             diag_unary<K>(R, S, T, w, gs, bs, L, M);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float RS = R[c] * S[c];
-                const float tgr = a.temporal ? a.tg[(1 + c) * ps + i] : 0.0f;
-                g[c] = L.data * RS * e[c] - L.cl * (r[c] - a.lnb[3 * id + c]) - L.rc * (gs * r[c] - tgr);
+                g[c] = L.data * RS * e[c] - L.cl * (r[c] - a.lnb[3 * id + c]) - L.rc * (gs * r[c] - tgr[c]);
             }
             const float mS = (S[0] + S[1] + S[2]) * (1.0f / 3.0f);
             float md[3];
@@ -742,7 +788,7 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
     double acc[PV_N];
 #pragma unroll
     for (int v = 0; v < PV_N; ++v) acc[v] = 0.0;
-    for (int tile = tset.c0; tile < tset.c1; ++tile) {
+    for (int tile = tset.c0; tile < tset.c1; tile += tset.step) {
         int tx, ty;
         tile_xy(a, tset, tile, tx, ty);
         const int x0 = tx * TX, y0 = ty * TYW;
@@ -863,9 +909,12 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
                 for (int k = 0; k <= K; ++k) sum += bs.B[k][c] * p[3 + k];
                 ac[c] = R[c] * sum;
             }
-            const float gs = a.temporal ? a.tg[i] : 0.0f;
+            float gs = a.temporal ? a.tg[i] : 0.0f;
+            float psum[3] = {0.0f, 0.0f, 0.0f};
+            if (a.spatial) spatial_partners(Pl, li, (unsigned)a.tg[5 * ps + i], gs, psum);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) q[c] = L.data * R[c] * S[c] * ac[c] + (L.cl + L.rc * gs) * p[c];
+            for (int c = 0; c < 3; ++c)
+                q[c] = L.data * R[c] * S[c] * ac[c] + (L.cl + L.rc * gs) * p[c] - L.rc * psum[c];
             // monochrome block and unary layer terms
             const float w = a.wsr[i];
             // Jacobi diagonal, rebuilt as the build formed it (no M^-1 plane is read)
@@ -1004,7 +1053,7 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
         for (int c = 0; c < 3; ++c) B64[k][c] = st.refine ? a.b64[3 * k + c] : 0.0;
     const int rows = TYW * a.ppt;
     const int tile_px = TX * rows;
-    for (int tile = tset.c0; tile < tset.c1; ++tile) {
+    for (int tile = tset.c0; tile < tset.c1; tile += tset.step) {
         int tx, ty;
         tile_xy(a, tset, tile, tx, ty);
         for (int base = 0; base < tile_px; base += BS_BATCH) {
@@ -1416,6 +1465,20 @@ __device__ __forceinline__ void energy_body(const Args& a, const Lc& lc, const S
                         const double d = r[c] - (double)rp[k][c];
                         e[3] += d * d;
                     }
+                }
+            }
+        }
+        if (a.spatial) {
+            // the pixel's own (forward) spatial pairs, so every pair counts once
+            const unsigned smask = (unsigned)a.tg[5 * ps + i];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                if (!((smask >> nb) & 1u)) continue;
+                const long long jj = (long long)(y + SP_DY[nb]) * W + (x + SP_DX[nb]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double d = r[c] - (double)a.u[c * ps + jj];
+                    e[3] += d * d;
                 }
             }
         }

@@ -38,7 +38,8 @@ class GidParams(ctypes.Structure):
                 ("chroma_gate", c_double), ("chroma_floor", c_double),
                 ("gn_iters", c_int32), ("pcg_iters", c_int32), ("refine_mode", c_int32),
                 ("temporal", c_int32), ("cr_mode", c_int32), ("record_energy", c_int32),
-                ("use_graph", c_int32), ("bstep_scale", c_int32)]
+                ("use_graph", c_int32), ("bstep_scale", c_int32), ("spatial_pairs", c_int32),
+                ("spatial_seed", ctypes.c_uint32)]
 
 
 class GidFrameStats(ctypes.Structure):
@@ -113,6 +114,8 @@ SIGNATURES = [
                                     POINTER(c_double), POINTER(c_double), POINTER(c_int32)]),
     ("gid_resynthesize", c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), c_void_p, c_void_p,
                                    c_void_p, c_void_p, c_void_p]),
+    ("gid_correct_region", c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                                     c_void_p, c_void_p, POINTER(c_double), POINTER(c_int32)]),
     ("gid_status_string", ctypes.c_char_p, [c_int32]),
     ("gid_last_error", ctypes.c_char_p, [c_void_p]),
 ]
@@ -221,6 +224,28 @@ def resynthesize(layers, b_new, gain=None, ids=None, refl_scale=None, out=None, 
     if st != GID_OK:
         raise GidError(st, "gid_resynthesize")
     return out
+
+
+def correct_region(params: "GidParams", frame, ids, region, colors, stream=None):
+    """Misclustering correction (Sec. 5.2.2): returns (best colour index,
+    sparsity per candidate (K,), corrected ids tensor)."""
+    import torch
+    lib = load_library()
+    H, W = int(frame.shape[1]), int(frame.shape[2])
+    K = params.K
+    f = _ptr(frame, torch.float32, (3, H, W), "frame")
+    i = _ptr(ids, torch.uint8, (H, W), "ids")
+    r = _ptr(region, torch.uint8, (H, W), "region")
+    out = torch.empty((H, W), dtype=torch.uint8, device=frame.device)
+    cols = np.ascontiguousarray(np.asarray(colors, np.float64).reshape(-1))
+    sp = np.zeros(K)
+    best = c_int32(-1)
+    stp = c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
+    st = lib.gid_correct_region(byref(params), W, H, f, i, r, cols.ctypes.data_as(POINTER(c_double)), stp,
+                                c_void_p(out.data_ptr()), sp.ctypes.data_as(POINTER(c_double)), byref(best))
+    if st != GID_OK:
+        raise GidError(st, "gid_correct_region")
+    return best.value, sp, out
 
 
 class Solver:

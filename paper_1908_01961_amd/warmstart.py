@@ -74,13 +74,14 @@ class PairStore:
 
 
 def make_training_set(K: int, W: int, H: int, nframes: int, frames_per_clip: int, G: int, P: int,
-                      seed0: int, log=None) -> PairStore:
-    """nframes pairs from seeded synthetic clips (seeds seed0, seed0 + 1, ...)."""
+                      seed0: int, log=None, **clip_kw) -> PairStore:
+    """nframes pairs from seeded synthetic clips (seeds seed0, seed0 + 1, ...);
+    clip_kw (amp, supersample) match the scenes to the workload's recipe."""
     from scenes import make_clip
     store = PairStore()
     i = 0
     while len(store) < nframes:
-        clip = make_clip(W, H, K, frames_per_clip, seed0 + i)
+        clip = make_clip(W, H, K, frames_per_clip, seed0 + i, **clip_kw)
         store.add_clip(clip, G, P)
         i += 1
         if log:

@@ -6,29 +6,32 @@ colours within 1e-3.
 One part of the method is discontinuous: the non-negativity reweighting of an
 indirect layer (Sec. 6.4.1) gives a zero weight where T > 0 and a weight up to
 lambda / eps = 5e5 where T <= 0, and that weight pins most indirect-layer
-values within 1e-4 of zero (at the start of the last step of the 640x480
-first frame, 37% of the pixels have some |T_k| < 1e-4 and 0.04% some
-|T_k| < 1e-7).  Where the oracle starts a Gauss-Newton step with such a value
-within rounding distance of zero, which branch the step takes is decided below
-the resolution of any FP32 implementation, and the branches end far apart
-(observed: an oracle value of -3.6e-9 at the start of the last step of that
-frame; the GPU's FP32 trajectory takes the other branch there and ends 1.2e-2
-from the oracle, its four neighbours 4e-3).  Fed the oracle's own state at
-every step, the GPU matches each step to ~2e-5 at every element of full-size
-frames (the per-step tests), so such splits come only from these branch points.
+values within 1e-4 of zero.  Where the oracle starts a Gauss-Newton step with
+such a value within rounding distance of zero, which branch the step takes is
+decided below the resolution of any FP32 implementation, and the branches end
+far apart (observed: an oracle value of -3.6e-9 at the start of the last step of
+the 640x480 first frame; the GPU's FP32 trajectory takes the other branch there
+and ends 1.2e-2 from the oracle, its four neighbours 4e-3).  Fed the oracle's
+own state at every step, the GPU matches each step to ~2e-5 at every element of
+full-size frames (the per-step tests), so such splits come only from these
+branch points.
 
-Both branches are executions of the method on states that differ below FP32
-resolution, so for whole schedules the base colours are compared at the full
-bar, the layers are held to the bar on all but a tiny fraction of elements
-(MAX_OVER_FRAC) with every element within LOOSE_BOUND, and the final energy
-must be within the bar of the oracle run with its unknowns stored in FP32 or of
-the oracle run storing them in FP64: the two runs differ only in how a state is
-rounded between steps, and on a small frame one branch point moves the total
-energy by more than the bar (96x54 K=10, frame 2: the FP32-storage oracle ends
-at 24887.7, the FP64-storage oracle and the GPU at 24894.7, the GPU's own
-energy of its state matching the oracle's energy function to 1e-9).  The
-report gives, at the worst element, the smallest |T| the oracle's own
-trajectory had at that pixel and its 4-neighbours at a step start.
+So every layer element over the bar must sit at a traced branch point: the
+oracle's own trajectory had, at the start of some Gauss-Newton step after the
+first, a |T_k| below BRANCH_EPS at that pixel or within BRANCH_RADIUS of it
+(4-neighbourhood steps), and the element must stay within LOOSE_BOUND.  An
+element over the bar anywhere else fails, whatever their number.  The pixels
+carrying such elements are reported as the frame's non-negativity branch flips,
+with the per-layer maximum and RMS errors.
+
+The final energy must be within the bar of the oracle run storing its unknowns
+in FP32 between steps (the GPU's storage); the oracle run storing them in FP64
+is accepted instead only for a frame with branch flips: the two runs differ
+only in how a state is rounded between steps, and one branch point can move a
+small frame's total energy by more than the bar (96x54 K=10, frame 2: the
+FP32-storage oracle ends at 24887.7, the FP64-storage oracle and the GPU at
+24894.7, the GPU's own energy of its state matching the oracle's energy
+function to 1e-9).
 """
 from __future__ import annotations
 
@@ -36,20 +39,26 @@ import numpy as np
 
 TOL_LAYER = 1e-3
 TOL_ENERGY = 1e-4
-MAX_OVER_FRAC = 1e-4
 LOOSE_BOUND = 5e-2
+BRANCH_EPS = 1e-6
+BRANCH_RADIUS = 2
 
 
-def nearest_branch_value(starts: list, y: int, x: int) -> float:
-    """Smallest |T_k| (any layer of the pixel and its 4-neighbours) at the start
-    of a Gauss-Newton step after the first, from the oracle's trajectory."""
+def nearest_branch_value(starts: list, y: int, x: int, radius: int = 1) -> float:
+    """Smallest |T_k| (any indirect or direct layer) within `radius` 4-neighbourhood
+    steps of pixel (y, x) at the start of a Gauss-Newton step after the first,
+    from the oracle's trajectory."""
     best = np.inf
     for g in range(1, len(starts)):
         T = starts[g][3:]
         H, W = T.shape[1:]
-        for yy, xx in ((y, x), (y - 1, x), (y + 1, x), (y, x - 1), (y, x + 1)):
-            if 0 <= yy < H and 0 <= xx < W:
-                best = min(best, float(np.abs(T[:, yy, xx]).min()))
+        for dy in range(-radius, radius + 1):
+            for dx in range(-radius, radius + 1):
+                if abs(dy) + abs(dx) > radius:
+                    continue
+                yy, xx = y + dy, x + dx
+                if 0 <= yy < H and 0 <= xx < W:
+                    best = min(best, float(np.abs(T[:, yy, xx]).min()))
     return best
 
 
@@ -57,25 +66,33 @@ def compare_frame(layers: np.ndarray, b: np.ndarray, energy: float, ref, P: int 
                   say=print, alt=None) -> dict:
     """Check one GPU frame result (layers (n, H, W) with R = exp(r) first, colours
     (K, 3), final energy) against an oracle FrameResult (keep_starts for the
-    branch report); alt is the same frame from the oracle run storing its
-    unknowns in the other precision (used for the energy only)."""
+    branch trace); alt is the same frame from the oracle run storing its
+    unknowns in FP64 (used for the energy of a frame with branch flips only)."""
     d = np.concatenate([np.abs(layers[:3] - np.exp(ref.u[:3])), np.abs(layers[3:] - ref.u[3:])])
-    n_over = int((d > TOL_LAYER).sum())
+    over = np.argwhere(d > TOL_LAYER)
+    n_over = len(over)
     worst = np.unravel_index(int(np.argmax(d)), d.shape)
     db = float(np.abs(np.asarray(b) - ref.b).max())
     erel = abs(energy - ref.energy) / abs(ref.energy)
-    if alt is not None:
-        erel = min(erel, abs(energy - alt.energy) / abs(alt.energy))
-    rep = dict(max=float(d.max()), worst=tuple(int(v) for v in worst), n_over=n_over, frac_over=n_over / d.size,
-               db=db, Erel=erel)
-    msg = (f"{label} |layers| max {d.max():.2e} at {rep['worst']}, {n_over} of {d.size} over {TOL_LAYER:g}, "
-           f"|db| {db:.2e}, Erel {erel:.2e}; per layer " + " ".join(f"{v:.1e}" for v in d.max(axis=(1, 2))))
-    if n_over and ref.starts:
-        rep["branch_value"] = nearest_branch_value(ref.starts, worst[1], worst[2])
-        msg += f"; oracle min |T| near the worst element at a step start: {rep['branch_value']:.1e}"
+    pixels = sorted({(int(y), int(x)) for _, y, x in over})
+    branch = {p: nearest_branch_value(ref.starts, p[0], p[1], BRANCH_RADIUS) for p in pixels} if ref.starts else {}
+    off_branch = [p for p in pixels if not (branch.get(p, np.inf) <= BRANCH_EPS)]
+    erel_alt = abs(energy - alt.energy) / abs(alt.energy) if alt is not None else np.inf
+    rms = np.sqrt((d ** 2).mean(axis=(1, 2)))
+    rep = dict(max=float(d.max()), worst=tuple(int(v) for v in worst), n_over=n_over, flips=len(pixels),
+               off_branch=off_branch, db=db, Erel=erel, Erel_alt=erel_alt, rms=rms.tolist(),
+               per_layer_max=d.max(axis=(1, 2)).tolist())
+    msg = (f"{label} |layers| max {d.max():.2e} at {rep['worst']}, {n_over} of {d.size} over {TOL_LAYER:g} "
+           f"at {len(pixels)} branch-flip pixel(s), |db| {db:.2e}, Erel {erel:.2e}"
+           + (f" (FP64-storage oracle {erel_alt:.2e})" if alt is not None else "")
+           + "; per layer max " + " ".join(f"{v:.1e}" for v in rep["per_layer_max"])
+           + "; RMS " + " ".join(f"{v:.1e}" for v in rms))
+    if pixels:
+        msg += "; oracle min |T| near them at a step start: " + " ".join(
+            f"{p}:{branch.get(p, np.inf):.1e}" for p in pixels[:8])
     say(msg)
-    assert n_over <= MAX_OVER_FRAC * d.size, rep
+    assert not off_branch, rep
     assert d.max() <= LOOSE_BOUND, rep
     assert db <= TOL_LAYER, rep
-    assert erel <= TOL_ENERGY, rep
+    assert erel <= TOL_ENERGY or (pixels and erel_alt <= TOL_ENERGY), rep
     return rep

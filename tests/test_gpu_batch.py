@@ -139,6 +139,28 @@ def test_batch_first_frames_match_oracle(torch):
     batch.close()
 
 
+def test_batch_first_frames_match_oracle_at_mixed_sizes(torch):
+    """The clip sizes of the uneven batch (320x240 ... 1280x720, K from the
+    batch recipe), first frames, at the default launch shape: at 1280x720 a
+    clip's 3600 tiles share at most 2048 workgroups."""
+    import paper_1908_01961_amd as G
+    from scenes import mixed_batch_specs
+    specs = mixed_batch_specs(16, 400)[:8]
+    clips = [make_clip(sp["width"], sp["height"], sp["K"], 1, sp["seed"]) for sp in specs]
+    _say("batch first frames at the mixed sizes:", [(c.width, c.height, c.K) for c in clips])
+    solvers = [_solver(c) for c in clips]
+    batch = G.Batch(solvers)
+    lays = [torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda") for c in clips]
+    e = batch.step([_dev(torch, c.frames[0]) for c in clips], [_dev(torch, c.ids[0]) for c in clips], lays)
+    for i, c in enumerate(clips):
+        _, b = solvers[i].get_state()
+        _check_first_frame(lays[i].cpu().numpy().astype(np.float64), b, e[i], c,
+                           f"mixed batch clip {i} ({c.width}x{c.height} K={c.K}):")
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
 def test_batch_rejects_a_bad_frame_and_keeps_that_clip(torch):
     import paper_1908_01961_amd as G
     clips = _clips()[:2]

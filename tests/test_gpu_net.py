@@ -153,6 +153,7 @@ def test_layer_weight_gradient_matches_reference(torch, layer):
 # ---------------------------------------------------------------- whole network
 
 CASE = dict(K=4, W=80, H=24)
+NLAYERS = 6      # conv layers, each storing BF16 activations (and, backward, BF16 gradients)
 
 
 def test_forward_matches_reference(torch):
@@ -168,9 +169,21 @@ def test_forward_matches_reference(torch):
     x = np.concatenate([frame, u]).astype(np.float64)
     du_ref, db_ref, _ = WS.forward(p, x)
     e_u, e_b = _rel(du, du_ref), _rel(db, db_ref)
+    # element by element: one BF16 step (2^-8 relative) of the element plus one
+    # step of the output's RMS per layer.  Each of the six layers stores its
+    # activations in BF16; an activation whose FP32 (GPU) and FP64 (oracle) sums
+    # straddle a rounding boundary moves by one step, and the later layers carry
+    # that change to the output at about the activations' scale.
+    step = 2.0 ** -8
+    bu = step * (np.abs(du_ref) + NLAYERS * np.sqrt((du_ref ** 2).mean()))
+    bb = step * (np.abs(db_ref) + NLAYERS * np.sqrt((db_ref ** 2).mean()))
+    ru = float((np.abs(du - du_ref) / bu).max())
+    rb = float((np.abs(db - db_ref) / bb).max())
     _say(f"forward: |du - ref| / |ref| = {e_u:.2e}, |db - ref| / |ref| = {e_b:.2e}, "
-         f"max |du - ref| = {np.abs(du - du_ref).max():.2e} (max |ref| {np.abs(du_ref).max():.2e})")
+         f"max |du - ref| = {np.abs(du - du_ref).max():.2e} (max |ref| {np.abs(du_ref).max():.2e}); "
+         f"element error / one-BF16-step bound: du {ru:.3f}, db {rb:.3f}")
     assert e_u <= 3e-3 and e_b <= 3e-5
+    assert ru <= 1.0 and rb <= 1.0
     net.close()
 
 
@@ -193,10 +206,16 @@ def test_gradients_match_reference(torch):
     gref = WS.backward(p, cache, g_du, g_db)
     _say(f"loss gpu {loss:.8e} ref {loss_ref:.8e}")
     assert loss == pytest.approx(loss_ref, rel=1e-5)
+    step = 2.0 ** -8
     for k in gref:
         e = _rel(gd[k], gref[k])
-        _say(f"  grad {k}: rel {e:.2e} (|ref| {np.linalg.norm(gref[k]):.2e})")
+        # element by element, as for the forward pass: the backward pass stores the
+        # loss gradient and every layer's input gradient in BF16 too
+        bound = step * (np.abs(gref[k]) + NLAYERS * np.sqrt((gref[k] ** 2).mean()))
+        r = float((np.abs(gd[k] - gref[k]) / bound).max())
+        _say(f"  grad {k}: rel {e:.2e} (|ref| {np.linalg.norm(gref[k]):.2e}), element error / bound {r:.3f}")
         assert e <= 1e-3, k
+        assert r <= 1.0, k
     net.close()
 
 
@@ -214,16 +233,29 @@ def test_adam_step_matches_reference(torch):
     g, _ = net.gradients(_dev(torch, frame), _dev(torch, u), _dev(torch, du_t), db_t, 1.0)
     net.train_step(_dev(torch, frame), _dev(torch, u), _dev(torch, du_t), db_t, lr)
     after = net.get_params()
-    # reference Adam step from the GPU's own gradient: checks the update rule alone
-    pd = {k: v.copy() for k, v in flat_to_dict(flat, K).items()}
-    gd = flat_to_dict(g, K)
-    m = {k: np.zeros_like(v) for k, v in pd.items()}
-    v = {k: np.zeros_like(v) for k, v in pd.items()}
-    WS.adam_step(pd, gd, m, v, 1, lr)
+    # the oracle's Adam step from the oracle's own gradient of the same loss
+    x = np.concatenate([frame, u]).astype(np.float64)
+    du, dbv, cache = WS.forward(p, x)
+    _, g_du, g_db = WS.mse_loss(du, dbv, du_t.astype(np.float64), db_t.astype(np.float64), 1.0)
+    gref = WS.backward(p, cache, g_du, g_db)
+    pd = {k: vv.copy() for k, vv in flat_to_dict(flat, K).items()}
+    m = {k: np.zeros_like(vv) for k, vv in pd.items()}
+    v = {k: np.zeros_like(vv) for k, vv in pd.items()}
+    WS.adam_step(pd, gref, m, v, 1, lr)
     ref = dict_to_flat(pd, K).astype(np.float64)
-    err = np.abs(after - ref).max()
-    _say(f"adam: max |p_gpu - p_ref| = {err:.2e} (step size {lr})")
-    assert err <= 1e-6
+    # Adam's first step is lr g / (|g| + eps) per parameter: it agrees wherever the
+    # two gradients agree in sign and are well above eps; elsewhere (gradients
+    # within their own difference of zero) the step is bounded by 2 lr
+    gflat = dict_to_flat(gref, K).astype(np.float64)
+    gdiff = np.abs(g.astype(np.float64) - gflat)
+    sure = np.abs(gflat) > 10.0 * gdiff + 1e-6
+    err = np.abs(after - ref)
+    _say(f"adam from the oracle's gradient: max |p_gpu - p_ref| = {err[sure].max():.2e} on {int(sure.sum())} of "
+         f"{sure.size} parameters with a certain gradient sign, {err[~sure].max() if (~sure).any() else 0.0:.2e} "
+         f"on the rest (step size {lr})")
+    assert sure.mean() > 0.9
+    assert err[sure].max() <= 1e-6
+    assert err.max() <= 2.0 * lr + 1e-6
     net.close()
 
 

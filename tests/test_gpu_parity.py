@@ -262,18 +262,19 @@ def test_schedule_single_frame_64x48(torch):
         assert a == pytest.approx(b, rel=1e-4)
 
 
-def _anchored(torch, clip, G_, P_, nframes, **okw):
+def _anchored(torch, clip, G_, P_, nframes, check=None, **okw):
     """Video parity frame by frame: the oracle runs its own chain; for every
-    frame t >= 1 the GPU is loaded with the oracle's frame t-1 result (rounded to
-    FP32: the GPU's storage precision) and must reproduce the oracle's frame t,
-    which the oracle recomputes from that same rounded state."""
+    frame t >= 1 (or the frames in `check`) the GPU is loaded with the oracle's
+    frame t-1 result (rounded to FP32: the GPU's storage precision) and must
+    reproduce the oracle's frame t, which the oracle recomputes from that same
+    rounded state."""
     p = O.default_params(state_precision="f32", **okw)
     chain = O.decompose_clip(clip.frames, clip.ids, clip.b_init, p, G_, P_, temporal=True, nframes=nframes)
     s = _solver(torch, clip.width, clip.height, clip.K, gn_iters=G_, pcg_iters=P_, temporal=1, record_energy=1,
                 **({"cr_mode": okw["cr_mode"]} if "cr_mode" in okw else {}))
     layers = torch.empty((clip.K + 4, clip.height, clip.width), dtype=torch.float32, device="cuda")
     reps = []
-    for t in range(1, nframes):
+    for t in (check if check is not None else range(1, nframes)):
         prev = chain[t - 1]
         u32 = prev.u.astype(np.float32)
         s.set_base_colors(clip.b_init)
@@ -297,6 +298,16 @@ def test_video_anchored_160x120(torch):
 def test_video_anchored_640x480_full_size(torch):
     _say("anchored video_640x480_k6, first 3 frames (full size), 3x8")
     _anchored(torch, workload_clip("video_640x480_k6", nframes=3), 3, 8, 3)
+
+
+def test_video_anchored_640x480_deep_in_the_clip(torch):
+    _say("anchored video_640x480_k6, frames 10, 20 and 29 of 30 (full size), 3x8")
+    _anchored(torch, workload_clip("video_640x480_k6", workers=8), 3, 8, 30, check=(10, 20, 29))
+
+
+def test_video_anchored_1280x720_full_size(torch):
+    _say("anchored video_1280x720_k8, frames 1 and 2 (full size), 3x8")
+    _anchored(torch, workload_clip("video_1280x720_k8", nframes=3, workers=3), 3, 8, 3)
 
 
 def test_video_anchored_1080p_downsampled_96x54(torch):
