@@ -426,6 +426,21 @@ gid_status gid_resynthesize(const float *layers_dev, int32_t width, int32_t heig
                             const double *b_new_host, const float *gain_host, const uint8_t *ids_dev,
                             const float *refl_scale_host, void *hip_stream, float *out_dev);
 
+/* gid_cluster_frame for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and results, with the scratch in a fixed device array
+ * of GID_CLUSTER_SCRATCH_BYTES (2.5 MiB) that every device the library runs on
+ * holds until the process ends, instead of a per-call allocation.  It calls no
+ * allocating routine; the host-side k-means works in fixed-size host arrays.
+ * Any frame size fits (the launches stride over the pixels with at most 512
+ * workgroups).  Calls on one device share that device's array and must not
+ * overlap (two concurrent calls race); each call writes every scratch value
+ * it reads, so nothing carries over from the previous call.
+ * Errors: as gid_cluster_frame, without GID_ERR_OUT_OF_MEMORY. */
+gid_status gid_cluster_frame_noalloc(const float *frame_dev, int32_t width, int32_t height, int32_t k_max,
+                                     double merge_dist, void *hip_stream, uint8_t *ids_dev, double *colors_host,
+                                     double *centres_host, int32_t *k_out);
+
 const char *gid_status_string(gid_status s);
 /* Last error message of this context (valid until its next call). */
 const char *gid_last_error(const gid_ctx *ctx);

@@ -112,6 +112,8 @@ SIGNATURES = [
     ("gid_set_warmstart", c_int32, [c_void_p, c_void_p]),
     ("gid_cluster_frame", c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,
                                     POINTER(c_double), POINTER(c_double), POINTER(c_int32)]),
+    ("gid_cluster_frame_noalloc", c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,
+                                            POINTER(c_double), POINTER(c_double), POINTER(c_int32)]),
     ("gid_resynthesize", c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), c_void_p, c_void_p,
                                    c_void_p, c_void_p, c_void_p]),
     ("gid_correct_region", c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_double),
@@ -180,10 +182,10 @@ def _dbl(arr, n):
     return a, a.ctypes.data_as(POINTER(c_double))
 
 
-def cluster_frame(frame, k_max: int = 10, merge_dist: float = 0.2, stream=None):
+def cluster_frame(frame, k_max: int = 10, merge_dist: float = 0.2, stream=None, noalloc: bool = False):
     """Base-colour initialisation of a clip from its first frame (Sec. 5.1):
     returns (ids uint8 tensor (H, W) on the frame's device, colours (k, 3) FP64,
-    centres (k, 3) FP64)."""
+    centres (k, 3) FP64).  noalloc uses the entry point with a fixed scratch array."""
     import torch
     lib = load_library()
     H, W = int(frame.shape[1]), int(frame.shape[2])
@@ -193,7 +195,8 @@ def cluster_frame(frame, k_max: int = 10, merge_dist: float = 0.2, stream=None):
     cen = np.zeros(3 * k_max)
     k = c_int32(0)
     sp = c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
-    st = lib.gid_cluster_frame(f, W, H, int(k_max), float(merge_dist), sp, c_void_p(ids.data_ptr()),
+    fn = lib.gid_cluster_frame_noalloc if noalloc else lib.gid_cluster_frame
+    st = fn(f, W, H, int(k_max), float(merge_dist), sp, c_void_p(ids.data_ptr()),
                                cols.ctypes.data_as(POINTER(c_double)), cen.ctypes.data_as(POINTER(c_double)),
                                byref(k))
     if st != GID_OK:
