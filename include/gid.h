@@ -266,12 +266,15 @@ const char *gid_batch_last_error(const gid_batch *b);
 
 /* ---- launch-shape autotuner ----
  * Choose the number of workgroups of the per-pixel launches for this context's
- * (width, height, K) by timing the stencil kernels of a layer step on the device
- * over the default (one tile per workgroup) and candidates 64..2048 up to the tile
- * count; another shape replaces the default only when it times at least 3% faster.
- * cache_path (may be NULL) is a text file of
- * "width height K workgroups" lines: a cached choice is reused, a new one appended.
- * Synchronous; changes no solver state other than scratch vectors. */
+ * (width, height, K) by timing the real layer-step kernels (the build and the
+ * params.pcg_iters PCG iterations) on the loaded frame over the default (one
+ * tile per workgroup) and candidates 64..2048 up to the tile count; another
+ * shape replaces the default only when it times at least 3% faster.
+ * cache_path (may be NULL) is a text file of "width height K workgroups" lines:
+ * a cached choice is reused, a new one appended.  Synchronous.  Needs a frame
+ * loaded (gid_load_frame or a decomposed frame; GID_ERR_STATE otherwise); the
+ * unknowns and colours are not changed, the PCG vectors are scratch, and the
+ * frame's breakdown count and logged <r, z> are left to the next frame's reset. */
 gid_status gid_autotune(gid_ctx *ctx, const char *cache_path, int32_t *workgroups_out);
 /* Set / read the workgroup count directly (8..2048, rounded to a multiple of 8). */
 gid_status gid_set_workgroups(gid_ctx *ctx, int32_t workgroups);

@@ -57,6 +57,7 @@ struct gid_ctx {
     int ppt = 1, ntx = 0, nty = 0, ntiles = 0, nblocks = 0, nb_bs = 0;
     // clip state
     bool colors_set = false, have_prev = false;
+    bool frame_ready = false;      // a frame's per-pixel data is loaded (the tuner times on it)
     int frame_index = 0;
     double binit_host[3 * KMAX] = {};
     // pending host outputs of the last frame
@@ -607,6 +608,7 @@ static gid_status load_frame_impl(gid_ctx* c, const float* frame, const uint8_t*
     const Step s{};
     GID_HIP(c, L1(c, c->stream, KN_SCAN, a, s));
     GID_HIP(c, L1(c, c->stream, KN_PRECOMPUTE, a, s));
+    c->frame_ready = true;
     return GID_OK;
 }
 
@@ -1251,14 +1253,16 @@ gid_status gid_autotune(gid_ctx* c, const char* cache_path, int32_t* chosen) {
         if (chosen) *chosen = c->nblocks;
         return GID_OK;
     }
-    // time the stencil kernels of a layer step (single-step forms: no solver state
-    // changes except the scratch vectors q and M^-1) for each candidate grid
+    // time the real layer-step kernels (the build and the P PCG iterations) on the
+    // loaded frame for each candidate grid; u and the colours are not changed
+    if (!c->frame_ready)
+        return fail(c, GID_ERR_STATE, "load or decompose a frame first: the tuner times the real layer step on it");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     GID_HIP(c, hipEventCreate(&e0));
     GID_HIP(c, hipEventCreate(&e1));
     // candidates: the default shape (one tile per workgroup up to NB_MAX) first,
     // then fixed counts; another shape replaces the default only when it is 3%
-    // faster, since the single-step proxy understates the PCG iteration's traffic
+    // faster (differences below that are within the run-to-run spread)
     const int def_nb = std::min((int)align_up((size_t)c->ntiles, 8), NB_MAX);
     const int cand[] = {def_nb, 64, 128, 256, 384, 512, 768, 1024, 1536, 2048};
     double best_ms = 1e30;
@@ -1268,19 +1272,17 @@ gid_status gid_autotune(gid_ctx* c, const char* cache_path, int32_t* chosen) {
         const int nbc = cand[ci];
         if (ci > 0 && (nbc == def_nb || nbc > (int)align_up((size_t)c->ntiles, 8))) continue;
         set_nblocks(c, nbc);
-        Args a = step_args(c);
-        Step s{};
-        s.debug = 1;
-        a.out = c->qA;
-        a.out2 = c->minv;
-        a.pdebug = c->pA;
+        const Args a = step_args(c);
         float ms_total = 0.0f;
         for (int rep = 0; rep < 4; ++rep) {
-            if (hipEventRecord(e0, c->stream) != hipSuccess ||
-                launch_kernel(KN_GN_BUILD, a, s, c->stream) != hipSuccess ||
-                launch_kernel(KN_PCG, a, s, c->stream) != hipSuccess ||
-                launch_kernel(KN_PCG, a, s, c->stream) != hipSuccess ||
-                hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            bool ok = hipEventRecord(e0, c->stream) == hipSuccess &&
+                      launch_kernel(KN_GN_BUILD, a, Step{}, c->stream) == hipSuccess;
+            for (int i = 0; ok && i < c->prm.pcg_iters; ++i) {
+                Step s{};
+                s.iter = i;
+                ok = launch_kernel(KN_PCG, a, s, c->stream) == hipSuccess;
+            }
+            if (!ok || hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 status = fail(c, GID_ERR_HIP, "autotune launch failed");
                 break;
             }

@@ -185,6 +185,10 @@ def test_autotune_chooses_and_caches_a_launch_shape(torch):
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tune.txt")
         s = _solver(c)
+        with pytest.raises(G.GidError) as e:          # the tuner times the real kernels on a loaded frame
+            s.autotune(path)
+        assert e.value.status == 5
+        s.load_frame(_dev(torch, c.frames[0]), _dev(torch, c.ids[0]))
         n1 = s.autotune(path)
         assert 8 <= n1 <= 2048 and n1 % 8 == 0
         s2 = _solver(c)
