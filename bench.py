@@ -121,18 +121,25 @@ class Video:
         self.frames = torch.from_numpy(clip.frames).cuda()
         self.ids = torch.from_numpy(clip.ids).cuda()
         self.layers = torch.empty((self.K + 4, self.H, self.W), dtype=torch.float32, device="cuda")
+        self.nb = 0
         s = self.solver()
         s.set_base_colors(clip.b_init)
         s.decompose_frame(self.frames[0], self.ids[0], self.layers)
         self.blob = s.save_state()
+        # the launch shape from the library's autotuner, timed on the real layer
+        # step of this frame (untimed here; every solver of the clip uses it)
+        self.nb = s.autotune(None)
         s.close()
         self.px = (self.F - 1) * self.W * self.H
 
     def solver(self, G_=None, P_=None):
         import paper_1908_01961_amd as G
-        return G.Solver(self.W, self.H, G.default_params(self.K, gn_iters=G_ or self.G, pcg_iters=P_ or self.P,
-                                                         temporal=1, refine_mode="every", record_energy=0,
-                                                         use_graph=1))
+        s = G.Solver(self.W, self.H, G.default_params(self.K, gn_iters=G_ or self.G, pcg_iters=P_ or self.P,
+                                                      temporal=1, refine_mode="every", record_energy=0,
+                                                      use_graph=1))
+        if self.nb:
+            s.set_workgroups(self.nb)
+        return s
 
     def pass_(self, s, targets=None, max_gn=0):
         """Frames 1..F-1 from the checkpoint; per-frame (energy, outer iterations)."""
@@ -425,7 +432,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "width": video.W, "height": video.H, "frames": video.F, "K": video.K,
                    "frames_timed": video.F - 1, "gn_iters": video.G, "pcg_iters": video.P, "temporal": True,
-                   "refine": "every", "graph": True,
+                   "refine": "every", "graph": True, "workgroups": video.nb,
                    "method": "learned warm start + energy-target continuation" if use_learned else "plain"},
         "roofline": main_res["roofline"],
         "cpu_baseline": cpu,
