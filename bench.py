@@ -292,8 +292,10 @@ def bench_video(args, clip, workload, learned=True):
 
 def bench_batch(args, clips):
     """Sixteen clips of mixed size (320x240 ... 1280x720), length (8-32 frames) and K
-    (4-8), all advanced one frame per call through shared launches (gid_batch_*),
-    against the same contexts solving the clips one after another.  Each clip's
+    (4-8), all advanced one frame per call through shared launches (gid_batch_*) in
+    both launch layouts (every kernel one launch over all clips, or one launch per
+    K; the figure is the layout the batch tuner keeps), against the same contexts
+    solving the clips one after another.  Each clip's
     launch shape comes from the autotuner (untimed).  A pass covers every frame of
     every clip, from the initial colours."""
     import tempfile
@@ -338,13 +340,21 @@ def bench_batch(args, clips):
         return (time.perf_counter() - t0) / steps
 
     steps = max(1, min(args.steps, 3))
-    t_b = timed(step_batch, steps)
+    t_lay = {}
+    for launch in ("one", "per_k"):          # both launch layouts of a batch step
+        batch.set_launch(launch)
+        t_lay[launch] = timed(step_batch, steps)
+    chosen = batch.autotune()                # the library's choice (timed on the clips' last frames)
+    t_b = t_lay[chosen]
     t_s = timed(step_sequential, steps)
-    log(f"batch of {len(clips)}: batched {px / t_b / 1e6:.1f} Mpx/s, one after another {px / t_s / 1e6:.1f} Mpx/s")
+    log(f"batch of {len(clips)}: one launch per kernel {px / t_lay['one'] / 1e6:.1f} Mpx/s, one launch per K "
+        f"{px / t_lay['per_k'] / 1e6:.1f} Mpx/s (tuner: {chosen}), one clip after another {px / t_s / 1e6:.1f} Mpx/s")
     batch.close()
     for s in solvers:
         s.close()
-    return dict(mpx_s=round(px / t_b / 1e6, 2), ms_per_pass=round(t_b * 1e3, 2),
+    return dict(mpx_s=round(px / t_b / 1e6, 2), ms_per_pass=round(t_b * 1e3, 2), launch=chosen,
+                one_launch_mpx_s=round(px / t_lay["one"] / 1e6, 2),
+                per_k_mpx_s=round(px / t_lay["per_k"] / 1e6, 2),
                 sequential_mpx_s=round(px / t_s / 1e6, 2), batched_over_sequential=round(t_s / t_b, 3),
                 pixels_per_pass=px, clips=[dict(width=c.width, height=c.height, frames=c.nframes, K=c.K,
                                                 workgroups=n) for c, n in zip(clips, shapes)])
@@ -359,8 +369,8 @@ def main() -> int:
     ap.add_argument("--frames", type=int, default=None, help="frames per clip (default: the workload's)")
     ap.add_argument("--learned", choices=("on", "off"), default="on")
     ap.add_argument("--train-frames", type=int, default=2000, help="training pairs for the learned warm start")
-    ap.add_argument("--extras", choices=("on", "off"), default="on",
-                    help="also the 640x480 and 1280x720 plain lines and the 16-clip batch")
+    ap.add_argument("--extras", choices=("on", "off", "batch"), default="on",
+                    help="also the 640x480 and 1280x720 plain lines and the 16-clip batch (batch: the batch only)")
     ap.add_argument("--cpu", choices=("on", "off"), default="on", help="time the FP64 oracle on the host")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device 5 times: a plain copy "
@@ -379,9 +389,9 @@ def main() -> int:
     clip = workload_clip(args.workload, nframes=F, gt=False, workers=GEN_WORKERS)
     log(f"generated {args.workload} ({F} frames) in {time.perf_counter() - t0:.1f} s")
     extra_clips = {}
-    if args.extras == "on":
+    if args.extras != "off":
         for name in ("video_640x480_k6", "video_1280x720_k8"):
-            if name != args.workload:
+            if name != args.workload and args.extras == "on":
                 extra_clips[name] = workload_clip(name, gt=False, workers=GEN_WORKERS)
         specs = mixed_batch_specs(16, 400)
         extra_clips["batch_16_mixed"] = [make_clip(sp["width"], sp["height"], sp["K"], sp["frames"], sp["seed"],

@@ -235,15 +235,27 @@ gid_status gid_set_profiling(gid_ctx *ctx, int32_t enable);
 gid_status gid_get_kernel_times(gid_ctx *ctx, double *ms_out, int64_t *launches_out);
 
 /* ---- batches of clips of uneven size ----
- * A batch groups contexts (each with its own frame size and K) that share the
- * stream, the schedule (gn_iters, pcg_iters, refine_mode) and record_energy = 0.
- * Every kernel of a batch step is one launch per K among the active clips (per
- * eight clips of one K): each workgroup finds its clip from a prefix table of
- * workgroup counts and runs that clip's kernel body, the clip descriptors
- * travelling in the kernel arguments; reductions stay per clip.  With use_graph
- * the outer iterations of a step are replayed from a graph cached per set of
- * active clips, refinement and set of clips with the temporal prior on. */
+ * Independent clips solved together (each clip is its own instance of the
+ * per-frame solve of Sec. 7.1, so batching changes no result).  A batch groups
+ * contexts (each with its own frame size and K) that share the stream, the
+ * schedule (gn_iters, pcg_iters, refine_mode) and record_energy = 0.  Each
+ * workgroup of a batched launch finds its clip from a prefix table of workgroup
+ * counts and runs that clip's kernel body over the clip's own launch shape;
+ * reductions stay per clip, so every clip's results equal a single-clip run bit
+ * for bit.  Two launch layouts:
+ *   GID_BATCH_ONE_LAUNCH (default): every kernel of a step is one launch over all
+ *     active clips whatever their K; the clip descriptors sit in a device table
+ *     uploaded ahead of the step, and the kernel carries the bodies of every K up
+ *     to the batch's largest (rounded up to 4, 8, 12 or 16), with that body's
+ *     registers and LDS;
+ *   GID_BATCH_PER_K: one launch per K among the active clips (per eight clips of
+ *     one K), the descriptors travelling in the kernel arguments and each kernel
+ *     compiled for exactly its K.
+ * With use_graph the outer iterations of a step are replayed from a graph cached
+ * per set of active clips, refinement, layout and set of clips with the temporal
+ * prior on. */
 typedef struct gid_batch gid_batch;
+enum { GID_BATCH_ONE_LAUNCH = 0, GID_BATCH_PER_K = 1 };
 
 /* Group n (1..64) distinct contexts into a batch.  Tune the contexts (gid_autotune,
  * gid_set_workgroups) before creating the batch.  Errors: GID_ERR_INVALID_ARG
@@ -263,6 +275,22 @@ gid_status gid_batch_decompose(gid_batch *b, const float *const *frames_dev,
  * was rejected (its state is unchanged) or its energy is not finite. */
 gid_status gid_batch_synchronize(gid_batch *b, double *energies_out);
 const char *gid_batch_last_error(const gid_batch *b);
+
+/* Choose the launch layout of later steps (GID_BATCH_ONE_LAUNCH or
+ * GID_BATCH_PER_K).  Errors: GID_ERR_INVALID_ARG (unknown layout), GID_ERR_STATE
+ * (a step is pending). */
+gid_status gid_batch_set_launch(gid_batch *b, int32_t mode);
+gid_status gid_batch_get_launch(const gid_batch *b, int32_t *mode_out);
+
+/* Time one outer iteration of every clip without its updates (the build, the
+ * pcg_iters PCG iterations and the base-colour sums, on each clip's loaded frame;
+ * unknowns and colours are not changed) under both layouts, best of five, and
+ * keep the one-launch layout unless the per-K one is 5% faster (the kernels left
+ * out of the timing favour the one-launch layout); chosen_out (may be NULL)
+ * receives the choice.  Synchronizes the stream.
+ * Errors: GID_ERR_STATE (a step is pending, or a clip has no loaded frame yet:
+ * run a step first). */
+gid_status gid_batch_autotune(gid_batch *b, int32_t *chosen_out);
 
 /* ---- launch-shape autotuner ----
  * Choose the number of workgroups of the per-pixel launches for this context's

@@ -14,7 +14,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libgid.so")
-SOURCES = ["gid_kernels.hip", "gid_api.hip", "gid_net_kernels.hip", "gid_net_api.hip", "gid_cluster.hip", "gid_cluster_noalloc.hip", "gid_resynth.hip", "gid_correct.hip"]
+SOURCES = ["gid_kernels.hip", "gid_table4.hip", "gid_table8.hip", "gid_table12.hip", "gid_table16.hip",
+           "gid_api.hip", "gid_net_kernels.hip", "gid_net_api.hip", "gid_cluster.hip", "gid_cluster_noalloc.hip",
+           "gid_resynth.hip", "gid_correct.hip"]
 ARCH = os.environ.get("GID_OFFLOAD_ARCH", "gfx950")
 
 # Every HIP file is compiled without packed-FP32 instruction selection.

@@ -1032,6 +1032,9 @@ struct gid_batch {
     // the descriptors are baked into the graph's kernel arguments
     std::map<std::tuple<unsigned long long, int, unsigned long long>, hipGraphExec_t> graphs;
     std::vector<int> active;           // clips of the pending step
+    int launch = GID_BATCH_ONE_LAUNCH; // launch layout of a step
+    ClipTable* d_table = nullptr;      // clip descriptors of the one-launch layout (device)
+    ClipTable* h_table = nullptr;      // their pinned staging copy
     bool pending = false;
     std::string err;
 };
@@ -1053,6 +1056,84 @@ void batch_release(gid_batch* b) {
     b->graphs.clear();
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->h_out) (void)hipHostFree(b->h_out);
+    if (b->h_table) (void)hipHostFree(b->h_table);
+    if (b->d_table) (void)hipFree(b->d_table);
+}
+
+// The launch layouts of one step over the active clips act (sorted by K) with
+// their descriptors: per-K groups of at most BATCH_LAUNCH_MAX clips, and the clip
+// table of the one-launch layout (filled in b->h_table; the caller uploads it).
+struct BatchPlan {
+    std::vector<BatchGrid> groups;
+    TableGrid table{};
+};
+
+// A buffer as the table stores it: its byte offset from the table's device
+// address, carried in the pointer field (0 for a null buffer).
+extern "C++" {
+template <typename T>
+T* table_offset(T* p, const void* table) {
+    if (!p) return nullptr;
+    const std::ptrdiff_t off = reinterpret_cast<const char*>(p) - static_cast<const char*>(table);
+    return reinterpret_cast<T*>(static_cast<std::uintptr_t>(off));
+}
+}
+
+void plan_batch(gid_batch* b, const std::vector<int>& act, const std::vector<Args>& args, BatchPlan& p) {
+    const int na = (int)act.size();
+    p.groups.clear();
+    for (int j = 0; j < na;) {
+        const int K = b->clips[act[j]]->K;
+        int m = 0;
+        while (j + m < na && m < BATCH_LAUNCH_MAX && b->clips[act[j + m]]->K == K) ++m;
+        BatchGrid g{};
+        g.ba.n = m;
+        g.ba.wg_pix[0] = g.ba.wg_bs[0] = 0;
+        for (int q = 0; q < m; ++q) {
+            const gid_ctx* c = b->clips[act[j + q]];
+            g.ba.a[q] = args[j + q];
+            g.ba.wg_pix[q + 1] = g.ba.wg_pix[q] + c->nblocks;
+            g.ba.wg_bs[q + 1] = g.ba.wg_bs[q] + c->nb_bs;
+        }
+        g.total_pix = g.ba.wg_pix[m];
+        g.total_bs = g.ba.wg_bs[m];
+        g.k = K;
+        p.groups.push_back(g);
+        j += m;
+    }
+    ClipTable* t = b->h_table;
+    t->n = na;
+    t->wg_pix[0] = t->wg_bs[0] = 0;
+    TableGrid& tg = p.table;
+    tg = TableGrid{};
+    tg.t = b->d_table;
+    tg.n = na;
+    for (int j = 0; j < na; ++j) {
+        const gid_ctx* c = b->clips[act[j]];
+        // the kernels decode every buffer as the table's device address plus a
+        // byte offset (0 for a null buffer)
+        Args e = args[j];
+#define GID_ENC(f) e.f = table_offset(e.f, b->d_table);
+        GID_TABLE_POINTERS(GID_ENC)
+#undef GID_ENC
+        t->a[j] = e;
+        t->wg_pix[j + 1] = t->wg_pix[j] + c->nblocks;
+        t->wg_bs[j + 1] = t->wg_bs[j] + c->nb_bs;
+        tg.kmax = std::max(tg.kmax, c->K);
+        tg.kmask |= 1u << c->K;
+    }
+    tg.total_pix = t->wg_pix[na];
+    tg.total_bs = t->wg_bs[na];
+}
+
+// Every launch of kernel k for one step under the batch's layout.
+hipError_t launch_plan(const gid_batch* b, const BatchPlan& p, Kern k, const Step& s, hipStream_t cs) {
+    if (b->launch == GID_BATCH_ONE_LAUNCH) return launch_table(k, p.table, s, cs);
+    for (const BatchGrid& g : p.groups) {
+        const hipError_t e = launch_batch(k, g, s, cs);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 }  // namespace
 
@@ -1077,11 +1158,18 @@ gid_status gid_batch_create(gid_ctx* const* ctxs, int32_t n, gid_batch** out) {
         b->clips.push_back(ctxs[i]);
         b->nb_snapshot.push_back(ctxs[i]->nblocks);
     }
-    if (hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(double) * 2 * n) != hipSuccess) {
+    int dev = 0;
+    bool ok = hipGetDevice(&dev) == hipSuccess && hipSetDevice(c0->device) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_out), sizeof(double) * 2 * n) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void**>(&b->h_table), sizeof(ClipTable)) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void**>(&b->d_table), sizeof(ClipTable)) == hipSuccess;
+    (void)hipSetDevice(dev);
+    if (!ok) {
         batch_release(b);
         delete b;
         return GID_ERR_OUT_OF_MEMORY;
     }
+    std::memset(b->h_table, 0, sizeof(ClipTable));
     *out = b;
     return GID_OK;
 }
@@ -1122,48 +1210,31 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
     if (mode == GID_REFINE_FIRST_FRAME && first_count != 0 && first_count != (int)act.size())
         return bfail(b, GID_ERR_UNSUPPORTED, "refine-first-frame needs the active clips at the same frame");
     const bool refine = mode == GID_REFINE_EVERY_STEP || (mode == GID_REFINE_FIRST_FRAME && first_count > 0);
-    // active clips grouped by K (clips keep their relative order inside a group),
-    // each group cut into launches of at most BATCH_LAUNCH_MAX clips; every kernel
-    // of the step is launched once per such launch
+    // active clips sorted by K (stable), their descriptors, and the step's launch
+    // layout: one launch per kernel over all of them (the clip table, uploaded
+    // ahead of the step's kernels in stream order), or one per K group
     std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return b->clips[x]->K < b->clips[y]->K; });
     const int na = (int)act.size();
-    std::vector<BatchGrid> groups;
+    std::vector<Args> args(na);
     unsigned long long tmask = 0;
-    for (int j = 0; j < na;) {
-        const int K = b->clips[act[j]]->K;
-        int m = 0;
-        while (j + m < na && m < BATCH_LAUNCH_MAX && b->clips[act[j + m]]->K == K) ++m;
-        BatchGrid g{};
-        g.ba.n = m;
-        g.ba.wg_pix[0] = g.ba.wg_bs[0] = 0;
-        for (int q = 0; q < m; ++q) {
-            const int i = act[j + q];
-            gid_ctx* c = b->clips[i];
-            Args a = base_args(c);
-            a.in_frame = frames[i];
-            a.in_ids = ids[i];
-            a.out = layers ? layers[i] : nullptr;
-            a.first = c->frame_index == 0;
-            a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
-            if (a.temporal) tmask |= 1ull << i;
-            g.ba.a[q] = a;
-            g.ba.wg_pix[q + 1] = g.ba.wg_pix[q] + c->nblocks;
-            g.ba.wg_bs[q + 1] = g.ba.wg_bs[q] + c->nb_bs;
-        }
-        g.total_pix = g.ba.wg_pix[m];
-        g.total_bs = g.ba.wg_bs[m];
-        g.k = K;
-        groups.push_back(g);
-        j += m;
+    for (int j = 0; j < na; ++j) {
+        const int i = act[j];
+        gid_ctx* c = b->clips[i];
+        Args a = base_args(c);
+        a.in_frame = frames[i];
+        a.in_ids = ids[i];
+        a.out = layers ? layers[i] : nullptr;
+        a.first = c->frame_index == 0;
+        a.temporal = (c->prm.temporal && c->have_prev) ? 1 : 0;
+        if (a.temporal) tmask |= 1ull << i;
+        args[j] = a;
     }
+    BatchPlan plan;
+    plan_batch(b, act, args, plan);
     hipStream_t st = b->stream;
-    auto each = [&](Kern k, const Step& s, hipStream_t cs) {
-        for (const BatchGrid& g : groups) {
-            const hipError_t e = launch_batch(k, g, s, cs);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    };
+    if (b->launch == GID_BATCH_ONE_LAUNCH)
+        GID_BHIP(b, hipMemcpyAsync(b->d_table, b->h_table, sizeof(ClipTable), hipMemcpyHostToDevice, st));
+    auto each = [&](Kern k, const Step& s, hipStream_t cs) { return launch_plan(b, plan, k, s, cs); };
     const Step s0{};
     GID_BHIP(b, each(KN_SCAN, s0, st));
     GID_BHIP(b, each(KN_PRECOMPUTE, s0, st));
@@ -1174,7 +1245,7 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
                                 [&](Kern k, const Step& s) { return each(k, s, cs); }, &ns);
     };
     if (prm.use_graph) {
-        const auto key = std::make_tuple(mask, refine ? 1 : 0, tmask);
+        const auto key = std::make_tuple(mask, (refine ? 1 : 0) | (b->launch << 1), tmask);
         auto it = b->graphs.find(key);
         if (it == b->graphs.end()) {
             hipGraphExec_t ex = nullptr;
@@ -1195,6 +1266,7 @@ gid_status gid_batch_decompose(gid_batch* b, const float* const* frames, const u
                                    hipMemcpyDeviceToHost, st));
         c->frame_index += 1;
         c->have_prev = true;
+        c->frame_ready = true;
     }
     b->active = act;
     b->pending = true;
@@ -1226,6 +1298,87 @@ gid_status gid_batch_synchronize(gid_batch* b, double* energies) {
 }
 
 const char* gid_batch_last_error(const gid_batch* b) { return b ? b->err.c_str() : "no batch"; }
+
+gid_status gid_batch_set_launch(gid_batch* b, int32_t mode) {
+    if (!b) return GID_ERR_INVALID_ARG;
+    if (mode != GID_BATCH_ONE_LAUNCH && mode != GID_BATCH_PER_K) return bfail(b, GID_ERR_INVALID_ARG, "unknown launch layout");
+    if (b->pending) return bfail(b, GID_ERR_STATE, "synchronize the pending batch step first");
+    b->launch = mode;
+    return GID_OK;
+}
+
+gid_status gid_batch_get_launch(const gid_batch* b, int32_t* mode) {
+    if (!b || !mode) return GID_ERR_INVALID_ARG;
+    *mode = b->launch;
+    return GID_OK;
+}
+
+gid_status gid_batch_autotune(gid_batch* b, int32_t* chosen) {
+    if (!b) return GID_ERR_INVALID_ARG;
+    if (b->pending) return bfail(b, GID_ERR_STATE, "synchronize the pending batch step first");
+    for (const gid_ctx* c : b->clips)
+        if (!c->frame_ready) return bfail(b, GID_ERR_STATE, "every clip needs a loaded frame: the tuner times the real layer step");
+    GID_BHIP(b, hipStreamSynchronize(b->stream));
+    const int n = (int)b->clips.size();
+    std::vector<int> act(n);
+    for (int i = 0; i < n; ++i) act[i] = i;
+    std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return b->clips[x]->K < b->clips[y]->K; });
+    std::vector<Args> args(n);
+    for (int j = 0; j < n; ++j) args[j] = step_args(b->clips[act[j]]);
+    BatchPlan plan;
+    plan_batch(b, act, args, plan);
+    GID_BHIP(b, hipMemcpyAsync(b->d_table, b->h_table, sizeof(ClipTable), hipMemcpyHostToDevice, b->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GID_BHIP(b, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return bfail(b, GID_ERR_HIP, "hipEventCreate failed");
+    }
+    // one outer iteration of every clip without its updates (the build, the
+    // pcg_iters PCG iterations and the base-colour sums; u and the colours are not
+    // changed) under each layout, the best of five repetitions after one that warms
+    // the caches.  The per-K layout is kept only when it is 5% faster: the
+    // kernels the timing leaves out (scan, solve, energy, output) favour the
+    // one-launch layout, which issues one launch where the other issues one per K.
+    const int saved = b->launch;
+    const int P = b->clips[0]->prm.pcg_iters;
+    const int modes[2] = {GID_BATCH_ONE_LAUNCH, GID_BATCH_PER_K};
+    double ms_of[2] = {1e30, 1e30};
+    gid_status status = GID_OK;
+    for (int mi = 0; mi < 2 && status == GID_OK; ++mi) {
+        b->launch = modes[mi];
+        for (int rep = 0; rep < 6; ++rep) {
+            bool ok = hipEventRecord(e0, b->stream) == hipSuccess &&
+                      launch_plan(b, plan, KN_GN_BUILD, Step{}, b->stream) == hipSuccess;
+            for (int i = 0; ok && i < P; ++i) {
+                Step s{};
+                s.iter = i;
+                ok = launch_plan(b, plan, KN_PCG, s, b->stream) == hipSuccess;
+            }
+            Step sb{};
+            sb.iter = P - 1;
+            sb.refine = 1;
+            sb.add_delta = 0;     // sums only: the layer step is not applied
+            ok = ok && launch_plan(b, plan, KN_APPLY_BSUM, sb, b->stream) == hipSuccess;
+            if (!ok || hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                status = bfail(b, GID_ERR_HIP, "batch autotune launch failed");
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep > 0) ms_of[mi] = std::min(ms_of[mi], (double)ms);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != GID_OK) {
+        b->launch = saved;
+        return status;
+    }
+    b->launch = ms_of[1] < 0.95 * ms_of[0] ? GID_BATCH_PER_K : GID_BATCH_ONE_LAUNCH;
+    if (chosen) *chosen = b->launch;
+    return GID_OK;
+}
 
 // ------------------------------------------------------------- autotuner
 

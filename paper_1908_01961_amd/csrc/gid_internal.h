@@ -70,7 +70,9 @@ struct Step {
     int check;      // energy total: compare with the frame's target after an outer iteration
 };
 
-// One clip: its geometry, parameters and every buffer a kernel may touch.
+// One clip: its geometry, parameters and every buffer a kernel may touch (every
+// pointer field is listed in GID_TABLE_POINTERS below, which the clip table
+// encodes and decodes).
 // Passed by value to single-clip launches and, up to BATCH_LAUNCH_MAX of them,
 // inside a BatchArgs to batched launches.
 struct Args {
@@ -160,8 +162,44 @@ struct BatchGrid {
     int k;                  // the K every clip of this launch has
 };
 
-// Launch one kernel for one clip / for a batch (returns the launch error).
+// Every active clip of a batch in one launch per kernel, whatever its K.  The
+// descriptors do not fit the kernel arguments, so they live in a device table
+// uploaded before the step; each workgroup finds its clip by a binary search over
+// the workgroup prefix sums and runs the body compiled for that clip's K.  A
+// kernel of this family holds the bodies of every K up to its bound (4, 8, 12 or
+// 16, the smallest at or above the largest K of the batch), so its registers and
+// dynamic LDS are those of the largest body.
+constexpr int TABLE_CLIPS_MAX = 64;
+// The pointer fields of Args; in a ClipTable each holds the byte offset of its
+// buffer from the table's device address (0 for a null buffer).
+#define GID_TABLE_POINTERS(X)                                                                         \
+    X(u) X(delta) X(zA) X(zB) X(pA) X(pB) X(qA) X(qB) X(minv) X(I) X(ids) X(wsr) X(tg) X(Iprev)        \
+    X(rprev) X(bf) X(lnb) X(bcf) X(b64) X(lnb64) X(binit64) X(scal) X(partials) X(tickets) X(elog)     \
+    X(bsum) X(in_frame) X(in_ids) X(out) X(out2) X(pdebug) X(ucand) X(dbc) X(b64c) X(lnb64c) X(bfc)    \
+    X(lnbc) X(bcfc)
+struct ClipTable {
+    int n;
+    int wg_pix[TABLE_CLIPS_MAX + 1];
+    int wg_bs[TABLE_CLIPS_MAX + 1];
+    Args a[TABLE_CLIPS_MAX];
+};
+
+struct TableGrid {
+    const ClipTable* t;     // device copy
+    int n, total_pix, total_bs;
+    int kmax;               // largest K of the clips
+    unsigned kmask;         // bit K set when a clip has that K
+};
+
+// Launch one kernel for one clip / for a batch of one K / for a whole batch
+// (returns the launch error).
 hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s);
 hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t s);
+hipError_t launch_table(Kern k, const TableGrid& g, const Step& st, hipStream_t s);
+// the four clip-table families (gid_table4.hip ... gid_table16.hip)
+hipError_t launch_table4(Kern k, const TableGrid& g, const Step& st, hipStream_t s);
+hipError_t launch_table8(Kern k, const TableGrid& g, const Step& st, hipStream_t s);
+hipError_t launch_table12(Kern k, const TableGrid& g, const Step& st, hipStream_t s);
+hipError_t launch_table16(Kern k, const TableGrid& g, const Step& st, hipStream_t s);
 
 }  // namespace gid

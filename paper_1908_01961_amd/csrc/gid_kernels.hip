@@ -17,9 +17,10 @@
 // Every kernel is a body over (clip descriptor, launch context, step); a
 // single-clip launch runs it over its whole grid, a batched launch runs it for
 // several clips of uneven size in one grid, each workgroup finding its clip
-// from a prefix table.  The clips of a batched launch share K (a batch with
-// several K issues one launch per K), so every kernel is compiled for exactly
-// its K and keeps that K's register allocation and occupancy.
+// from a prefix table.  The clips of a batched launch here share K (one launch
+// per K), so every kernel is compiled for exactly its K and keeps that K's
+// register allocation and occupancy; gid_kernels_table.inc builds the kernels
+// that take a whole batch of mixed K in one launch.
 //
 // Precision: unknowns and PCG vectors are FP32; every dot product, alpha, beta,
 // base-colour sum, the 3K x 3K solve and the energy are FP64.  Reductions are
@@ -159,9 +160,12 @@ __device__ __forceinline__ void block_sums(double* v, double* sh) {
 // PCG vectors of iteration i (ping-pong by parity; the build writes p0 = z0 into
 // the even p buffer).
 __device__ __forceinline__ int pcg_site(int i) { return (i & 1) ? R_PCGB : R_PCGA; }
-__device__ __forceinline__ float* p_buf(const Args& a, int i) { return (i & 1) ? a.pB : a.pA; }
-__device__ __forceinline__ float* z_buf(const Args& a, int i) { return (i & 1) ? a.zB : a.zA; }
-__device__ __forceinline__ float* q_buf(const Args& a, int i) { return (i & 1) ? a.qB : a.qA; }
+// (both fields are read and the values selected, so that a descriptor held in
+// registers is never addressed through a selected field address)
+__device__ __forceinline__ float* pick(int i, float* even, float* odd) { return (i & 1) ? odd : even; }
+__device__ __forceinline__ float* p_buf(const Args& a, int i) { return pick(i, a.pA, a.pB); }
+__device__ __forceinline__ float* z_buf(const Args& a, int i) { return pick(i, a.zA, a.zB); }
+__device__ __forceinline__ float* q_buf(const Args& a, int i) { return pick(i, a.qA, a.qB); }
 
 // The step length of PCG iteration i and the preconditioned residual norm that
 // follows it, from the sums the iteration published:
@@ -767,12 +771,14 @@ __device__ __forceinline__ void pcg_body(const Args& a, const Lc& lc, const Step
         // directions (p = z)
         betaf = ps_.rz_next > 0.0 ? (float)(ps_.rz_next / ps_.rz) : 0.0f;
     }
-    const float* pold = dbg ? a.pdebug : p_buf(a, first ? 0 : it - 1);
-    const float* zold = it <= 1 ? a.pA : z_buf(a, it - 1);     // z0 = p0
+    const float* pdbg = a.pdebug;
+    const float* pold = dbg ? pdbg : p_buf(a, first ? 0 : it - 1);
+    const float* zold = it <= 1 ? p_buf(a, 0) : z_buf(a, it - 1);     // z0 = p0
     const float* qold = q_buf(a, it - 1);                        // M^-1 q of iteration it-1
     float* pcur = p_buf(a, it);
     float* zcur = z_buf(a, it);
-    float* qcur = dbg ? a.out : q_buf(a, it);
+    float* const out = a.out;
+    float* qcur = dbg ? out : q_buf(a, it);
     const Lam L = a.lam;
     const long long ps = a.ps;
     const int W = a.W, H = a.H;
@@ -1773,6 +1779,15 @@ hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t 
             default: break;
         }
     });
+}
+
+hipError_t launch_table(Kern k, const TableGrid& g, const Step& st, hipStream_t s) {
+    if (g.n < 1 || g.n > TABLE_CLIPS_MAX || g.kmax < 1 || g.kmax > KMAX || (g.kmask >> (g.kmax + 1)) != 0)
+        return hipErrorInvalidValue;
+    if (g.kmax <= 4) return launch_table4(k, g, st, s);
+    if (g.kmax <= 8) return launch_table8(k, g, st, s);
+    if (g.kmax <= 12) return launch_table12(k, g, st, s);
+    return launch_table16(k, g, st, s);
 }
 
 #endif  // GID_KERNELS_ONLY

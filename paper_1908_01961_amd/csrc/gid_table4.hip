@@ -1,0 +1,3 @@
+// The clip-table kernels (one launch over a batch of mixed K) of the family bounded by K <= 4.
+#define GID_TABLE_KB 4
+#include "gid_kernels_table.inc"

@@ -118,6 +118,9 @@ SIGNATURES = [
                                    c_void_p, c_void_p, c_void_p]),
     ("gid_correct_region", c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p, POINTER(c_double),
                                      c_void_p, c_void_p, POINTER(c_double), POINTER(c_int32)]),
+    ("gid_batch_set_launch", c_int32, [c_void_p, c_int32]),
+    ("gid_batch_get_launch", c_int32, [c_void_p, POINTER(c_int32)]),
+    ("gid_batch_autotune", c_int32, [c_void_p, POINTER(c_int32)]),
     ("gid_status_string", ctypes.c_char_p, [c_int32]),
     ("gid_last_error", ctypes.c_char_p, [c_void_p]),
 ]
@@ -130,6 +133,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libgid.so is not built ({path}); run python -m paper_1908_01961_amd.build")
+    # torch brings its own HIP runtime: loaded first, it is the one the library
+    # binds to, so that torch's streams and allocations are valid in library calls
+    # (loading the library first would bind it to a second runtime)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)
@@ -533,8 +540,12 @@ class Net:
         return gw.reshape(cout, cin, 3, 3), gb
 
 
+BATCH_LAUNCH = {"one": 0, "per_k": 1}
+
+
 class Batch:
-    """Clips of uneven size solved together: one launch per kernel per step."""
+    """Clips of uneven size solved together: by default one launch per kernel per
+    step over all clips whatever their K, or one launch per K."""
 
     def __init__(self, solvers):
         self.lib = load_library()
@@ -576,6 +587,22 @@ class Batch:
     def step(self, frames, ids, layers=None):
         self.step_async(frames, ids, layers)
         return self.synchronize()
+
+    def set_launch(self, mode: str):
+        """'one' (every kernel one launch over all clips) or 'per_k' (one launch per K)."""
+        self._check(self.lib.gid_batch_set_launch(self.h, BATCH_LAUNCH[mode]), "gid_batch_set_launch")
+
+    @property
+    def launch(self) -> str:
+        m = c_int32()
+        self._check(self.lib.gid_batch_get_launch(self.h, byref(m)), "gid_batch_get_launch")
+        return {v: k for k, v in BATCH_LAUNCH.items()}[m.value]
+
+    def autotune(self) -> str:
+        """Time both launch layouts on the clips' loaded frames and keep the faster."""
+        m = c_int32()
+        self._check(self.lib.gid_batch_autotune(self.h, byref(m)), "gid_batch_autotune")
+        return {v: k for k, v in BATCH_LAUNCH.items()}[m.value]
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

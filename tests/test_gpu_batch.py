@@ -1,8 +1,8 @@
-"""Batched clips of uneven size and the launch-shape autotuner, through the C ABI.
+"""Batched clips of uneven size and the launch-shape autotuners, through the C ABI.
 
 A batch runs the same kernel bodies as single clips with the same per-clip
-workgroup layout and reduction order, so its results must equal per-clip runs
-bitwise; the first frames are also checked against the FP64 oracle at the
+workgroup layout and reduction order, in either launch layout (one launch over
+all clips, or one per K), so its results must equal per-clip runs bitwise; the first frames are also checked against the FP64 oracle at the
 parity bar (layers 1e-3 absolute, energy 1e-4 relative)."""
 import os
 import sys
@@ -59,11 +59,8 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def test_batch_equals_single_clips_bitwise(torch):
-    import paper_1908_01961_amd as G
-    clips = _clips()
-    _say("batch of", [(c.width, c.height, c.K, c.nframes) for c in clips])
-    single = []
+def _single_runs(torch, clips):
+    out_all = []
     for c in clips:
         s = _solver(c)
         out = []
@@ -72,9 +69,16 @@ def test_batch_equals_single_clips_bitwise(torch):
             _, st = s.decompose_frame(_dev(torch, c.frames[t]), _dev(torch, c.ids[t]), lay)
             out.append((lay.cpu().numpy().copy(), st["energy_final"]))
         s.close()
-        single.append(out)
+        out_all.append(out)
+    return out_all
+
+
+def _batch_equals(torch, clips, single, launch):
+    import paper_1908_01961_amd as G
     solvers = [_solver(c) for c in clips]
     batch = G.Batch(solvers)
+    batch.set_launch(launch)
+    assert batch.launch == launch
     lays = [torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda") for c in clips]
     for t in range(max(c.nframes for c in clips)):
         frames = [_dev(torch, c.frames[t]) if t < c.nframes else None for c in clips]
@@ -84,46 +88,73 @@ def test_batch_equals_single_clips_bitwise(torch):
             if t >= c.nframes:
                 assert np.isnan(e[i])
                 continue
-            assert np.array_equal(lays[i].cpu().numpy(), single[i][t][0]), (i, t)
-            assert e[i] == single[i][t][1], (i, t)
+            assert np.array_equal(lays[i].cpu().numpy(), single[i][t][0]), (launch, i, t)
+            assert e[i] == single[i][t][1], (launch, i, t)
     batch.close()
     for s in solvers:
         s.close()
 
 
-def test_batch_of_one_K_splits_into_launches_bitwise(torch):
-    """Eleven clips of one K: a step issues two launches (eight clips, then three);
-    clips that end early change the active set and the temporal flags between
-    steps.  Every clip equals its single-clip run bit for bit."""
+def test_one_launch_across_K_families_bitwise(torch):
+    """K = 2, 9 and 13 in one batch: the one-launch layout takes the family
+    bounded by 16 (every body up to K = 16 in one kernel); both layouts equal the
+    single-clip runs bit for bit."""
+    clips = [make_clip(W, H, K, F, s) for (W, H, K, F, s) in
+             [(70, 40, 2, 2, 431), (96, 36, 9, 3, 432), (64, 50, 13, 2, 433)]]
+    _say("batch across K families:", [(c.width, c.height, c.K, c.nframes) for c in clips])
+    single = _single_runs(torch, clips)
+    for launch in ("one", "per_k"):
+        _batch_equals(torch, clips, single, launch)
+
+
+def test_batch_launch_layout_calls(torch):
+    """The layout switch refuses unknown layouts and pending steps; the tuner needs
+    every clip's frame and then keeps one of the two layouts; a step after tuning
+    still equals the single-clip run bit for bit."""
     import paper_1908_01961_amd as G
+    clips = _clips()[:3]
+    single = _single_runs(torch, clips)
+    solvers = [_solver(c) for c in clips]
+    batch = G.Batch(solvers)
+    assert batch.launch == "one"                      # the default
+    with pytest.raises(G.GidError) as e:
+        batch.autotune()                              # no frame loaded yet
+    assert e.value.status == 5
+    assert solvers[0].lib.gid_batch_set_launch(batch.h, 7) == 1
+    lays = [torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda") for c in clips]
+    batch.step_async([_dev(torch, c.frames[0]) for c in clips], [_dev(torch, c.ids[0]) for c in clips], lays)
+    assert solvers[0].lib.gid_batch_set_launch(batch.h, 1) == 5   # a step is pending
+    batch.synchronize()
+    chosen = batch.autotune()
+    assert chosen in ("one", "per_k") and batch.launch == chosen
+    _say("batch tuner chose", chosen)
+    e1 = batch.step([_dev(torch, c.frames[1]) for c in clips], [_dev(torch, c.ids[1]) for c in clips], lays)
+    for i, c in enumerate(clips):
+        assert np.array_equal(lays[i].cpu().numpy(), single[i][1][0]), i
+        assert e1[i] == single[i][1][1], i
+    batch.close()
+    for s in solvers:
+        s.close()
+
+
+@pytest.mark.parametrize("launch", ["one", "per_k"])
+def test_batch_equals_single_clips_bitwise(torch, launch):
+    clips = _clips()
+    _say("batch of", [(c.width, c.height, c.K, c.nframes) for c in clips], "launch", launch)
+    _batch_equals(torch, clips, _single_runs(torch, clips), launch)
+
+
+@pytest.mark.parametrize("launch", ["one", "per_k"])
+def test_batch_of_one_K_splits_into_launches_bitwise(torch, launch):
+    """Eleven clips of one K: per K, a step issues two launches (eight clips, then
+    three); in one launch all eleven share the grid.  Clips that end early change
+    the active set and the temporal flags between steps.  Every clip equals its
+    single-clip run bit for bit."""
     sizes = [(40, 24), (64, 16), (72, 40), (48, 48), (96, 20), (33, 17), (64, 64), (80, 36),
              (56, 30), (100, 12), (45, 45)]
     clips = [make_clip(W, H, 4, 2 + (j % 3), 420 + j) for j, (W, H) in enumerate(sizes)]
-    _say("batch of one K:", [(c.width, c.height, c.nframes) for c in clips])
-    single = []
-    for c in clips:
-        s = _solver(c)
-        lay = torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda")
-        out = []
-        for t in range(c.nframes):
-            _, st = s.decompose_frame(_dev(torch, c.frames[t]), _dev(torch, c.ids[t]), lay)
-            out.append((lay.cpu().numpy().copy(), st["energy_final"]))
-        s.close()
-        single.append(out)
-    solvers = [_solver(c) for c in clips]
-    batch = G.Batch(solvers)
-    lays = [torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda") for c in clips]
-    for t in range(max(c.nframes for c in clips)):
-        frames = [_dev(torch, c.frames[t]) if t < c.nframes else None for c in clips]
-        ids = [_dev(torch, c.ids[t]) if t < c.nframes else None for c in clips]
-        e = batch.step(frames, ids, lays)
-        for i, c in enumerate(clips):
-            if t < c.nframes:
-                assert np.array_equal(lays[i].cpu().numpy(), single[i][t][0]), (i, t)
-                assert e[i] == single[i][t][1], (i, t)
-    batch.close()
-    for s in solvers:
-        s.close()
+    _say("batch of one K:", [(c.width, c.height, c.nframes) for c in clips], "launch", launch)
+    _batch_equals(torch, clips, _single_runs(torch, clips), launch)
 
 
 def test_batch_first_frames_match_oracle(torch):
