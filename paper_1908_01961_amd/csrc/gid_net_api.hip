@@ -42,7 +42,7 @@ struct gid_net {
 
 namespace {
 
-constexpr int WGRAD_PARTS = 256;
+constexpr int WGRAD_PARTS = 1024;   // four workgroups per CU: one per CU left the weight gradients latency-bound
 
 gid_status nfail(gid_net* net, gid_status s, const std::string& msg) {
     if (net) net->err = msg;

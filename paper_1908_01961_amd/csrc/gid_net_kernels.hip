@@ -276,22 +276,41 @@ __global__ __launch_bounds__(CONV_THREADS) void k_wgrad(WgradArgs a) {
     }
 }
 
-// Sum the per-workgroup weight and bias gradients in workgroup order into the
-// flat gradient (layout w[o][c][dy][dx], then b[o]).
-__global__ void k_wgrad_reduce(const float* gw_part, const float* gb_part, int nparts, int cin, int cout,
-                               float* grad_w, float* grad_b) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nw = cout * cin * 9;
-    if (e < nw) {
-        const int tap = e % 9, c = (e / 9) % cin, o = e / (9 * cin);
-        float s = 0.0f;
-        for (int p = 0; p < nparts; ++p) s += gw_part[((long long)p * 9 + tap) * C * C + o * C + c];
-        grad_w[e] = s;
-    } else if (e < nw + cout) {
-        const int o = e - nw;
-        float s = 0.0f;
-        for (int p = 0; p < nparts; ++p) s += gb_part[p * C + o];
-        grad_b[o] = s;
+// Sum the per-workgroup weight and bias gradients into the flat gradient (layout
+// w[o][c][dy][dx], then b[o]).  A workgroup takes 64 entries of the partials' own
+// layout (tap, o, c) -- the last workgroup the biases -- so that a wavefront's
+// partial reads are contiguous; its 16 wavefronts sum 16 contiguous ranges of
+// workgroups in order, and wavefront 0 adds the 16 range sums in order.  Entries
+// beyond cin x cout of a narrower layer are skipped.
+constexpr int WRED_WAVES = 16;
+__global__ __launch_bounds__(64 * WRED_WAVES) void k_wgrad_reduce(const float* gw_part, const float* gb_part,
+                                                                  int nparts, int cin, int cout, float* grad_w,
+                                                                  float* grad_b) {
+    constexpr int NE = 9 * C * C;
+    __shared__ float red[WRED_WAVES][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool bias = (int)blockIdx.x * 64 >= NE;
+    const int e = bias ? lane : (int)blockIdx.x * 64 + lane;
+    const float* src = bias ? gb_part : gw_part;
+    const long long stride = bias ? C : NE;
+    const bool live = bias ? e < cout : true;
+    const int p0 = (int)((long long)nparts * wv / WRED_WAVES), p1 = (int)((long long)nparts * (wv + 1) / WRED_WAVES);
+    float s = 0.0f;
+    if (live) {
+#pragma unroll 8
+        for (int p = p0; p < p1; ++p) s += src[(long long)p * stride + e];
+    }
+    red[wv][lane] = s;
+    __syncthreads();
+    if (wv != 0 || !live) return;
+    float t = red[0][lane];
+#pragma unroll
+    for (int g = 1; g < WRED_WAVES; ++g) t += red[g][lane];
+    if (bias) {
+        grad_b[e] = t;
+    } else {
+        const int c = e % C, o = (e / C) % C, tap = e / (C * C);
+        if (c < cin && o < cout) grad_w[(o * cin + c) * 9 + tap] = t;
     }
 }
 
@@ -464,9 +483,9 @@ long long conv_waves(int W, int H) { return (long long)conv_grid(W, H) * CONV_RO
 hipError_t launch_wgrad(const WgradArgs& a, int nparts, int cin, int cout, float* grad_w, float* grad_b,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_wgrad, dim3(nparts), dim3(CONV_THREADS), 0, s, a);
-    const int ne = cout * cin * 9 + cout;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((ne + 255) / 256), dim3(256), 0, s, a.gw_part, a.gb_part, nparts, cin,
-                       cout, grad_w, grad_b);
+    // 9 C C / 64 workgroups of weight entries, then one of biases
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(9 * C * C / 64 + 1), dim3(64 * WRED_WAVES), 0, s, a.gw_part, a.gb_part,
+                       nparts, cin, cout, grad_w, grad_b);
     return hipGetLastError();
 }
 

@@ -142,6 +142,31 @@ def bench_forward(K: int, W: int, H: int, reps: int = 20) -> float:
     return ms
 
 
+def bench_train_step(K: int, W: int, H: int, reps: int = 20) -> float:
+    """Milliseconds per training step (forward, loss gradient, input and weight
+    gradients of every layer, Adam) at W x H on random inputs and targets."""
+    import torch
+    net = Net(K, W, H)
+    flat = init_params(K, 1)
+    flat[flat == 0] = 0.01
+    net.set_params(flat)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    fr = torch.rand((3, H, W), device="cuda", generator=g)
+    u = torch.rand((K + 4, H, W), device="cuda", generator=g)
+    du = 0.01 * torch.randn((K + 4, H, W), device="cuda", generator=g)
+    db = np.zeros(3 * K, np.float32)
+    for _ in range(3):
+        net.train_step(fr, u, du, db, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.train_step(fr, u, du, db, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    net.close()
+    return ms
+
+
 def net_ptr(t):
     from ctypes import c_void_p
     return c_void_p(t.data_ptr())
@@ -149,11 +174,16 @@ def net_ptr(t):
 
 if __name__ == "__main__":
     import argparse
-    ap = argparse.ArgumentParser(description="time the warm-start network's forward pass")
+    ap = argparse.ArgumentParser(description="time the warm-start network's forward pass or training step")
     ap.add_argument("--width", type=int, default=1280)
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--K", type=int, default=8)
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--train", action="store_true", help="time a training step instead of a forward pass")
     a = ap.parse_args()
-    print(f"network forward {a.width}x{a.height} K={a.K}: {bench_forward(a.K, a.width, a.height, a.reps):.3f} ms",
-          flush=True)
+    if a.train:
+        print(f"network training step {a.width}x{a.height} K={a.K}: "
+              f"{bench_train_step(a.K, a.width, a.height, a.reps):.3f} ms", flush=True)
+    else:
+        print(f"network forward {a.width}x{a.height} K={a.K}: {bench_forward(a.K, a.width, a.height, a.reps):.3f} ms",
+              flush=True)
