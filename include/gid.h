@@ -296,8 +296,9 @@ gid_status gid_batch_autotune(gid_batch *b, int32_t *chosen_out);
  * Choose the number of workgroups of the per-pixel launches for this context's
  * (width, height, K) by timing the real layer-step kernels (the build and the
  * params.pcg_iters PCG iterations) on the loaded frame over the default (one
- * tile per workgroup) and candidates 64..2048 up to the tile count; another
- * shape replaces the default only when it times at least 3% faster.
+ * tile per workgroup) and every multiple of 64 from 64 to 2048 up to the tile
+ * count; another shape replaces the default only when it times at least 3%
+ * faster.
  * cache_path (may be NULL) is a text file of "width height K workgroups" lines:
  * a cached choice is reused, a new one appended.  Synchronous.  Needs a frame
  * loaded (gid_load_frame or a decomposed frame; GID_ERR_STATE otherwise); the

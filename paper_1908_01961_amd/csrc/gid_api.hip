@@ -1416,12 +1416,16 @@ gid_status gid_autotune(gid_ctx* c, const char* cache_path, int32_t* chosen) {
     // candidates: the default shape (one tile per workgroup up to NB_MAX) first,
     // then fixed counts; another shape replaces the default only when it is 3%
     // faster (differences below that are within the run-to-run spread)
+    // (every multiple of 64 up to NB_MAX: the best count sits near the number of
+    // workgroups the CUs hold at once, which depends on K, and a count that deals
+    // the tiles evenly avoids a partly filled last round)
     const int def_nb = std::min((int)align_up((size_t)c->ntiles, 8), NB_MAX);
-    const int cand[] = {def_nb, 64, 128, 256, 384, 512, 768, 1024, 1536, 2048};
+    std::vector<int> cand{def_nb};
+    for (int v = 64; v <= NB_MAX; v += 64) cand.push_back(v);
     double best_ms = 1e30;
     int best = c->nblocks;
     gid_status status = GID_OK;
-    for (int ci = 0; ci < (int)(sizeof(cand) / sizeof(cand[0])); ++ci) {
+    for (int ci = 0; ci < (int)cand.size(); ++ci) {
         const int nbc = cand[ci];
         if (ci > 0 && (nbc == def_nb || nbc > (int)align_up((size_t)c->ntiles, 8))) continue;
         set_nblocks(c, nbc);

@@ -23,7 +23,7 @@ constexpr int JUDGE_PREV_SLOT = ELOG_SLOTS - 4;    // warm-start judge: energy a
 constexpr int JUDGE_NET_SLOT = ELOG_SLOTS - 3;     // warm-start judge: energy at the network's prediction
 constexpr int ELOG_FINAL_SLOT = ELOG_SLOTS - 2;    // the frame's final energy when half-steps are not recorded
 constexpr int NB_TUNE_MAX = 2048;   // workgroups of a per-pixel launch (at most)
-constexpr int NB_BS_MAX = 512;   // workgroups of the apply + base-colour-sum pass (at most)
+constexpr int NB_BS_MAX = 1024;  // workgroups of the apply + base-colour-sum pass (at most)
 
 // Slots of the device scalar array (doubles).
 enum Scal : int {

@@ -613,29 +613,55 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
         int tx, ty;
         tile_xy(a, tset, tile, tx, ty);
         const int x0 = tx * TX, y0 = ty * TYW;
-        for (int idx = threadIdx.x; idx < HN; idx += NTHREADS) {
+        const int x = x0 + lx, y = y0 + ly;
+        const bool own_in = x < W && y < H;
+        const long long i = own_in ? (long long)y * W + x : 0;   // off-frame: read pixel 0, unused
+        // every load of the tile in one batch: the own pixel's per-pixel data, then
+        // the two elements of the 66 x 6 unknowns tile this thread stages (the second
+        // only for the first 140 threads; off-frame elements read pixel 0, masked)
+        float Iv[3];
+        load3(a.I, ps, i, Iv);
+        const int id = a.ids[i];
+        const float w = a.wsr[i];
+        float gs = 0.0f, tgr[3] = {0.0f, 0.0f, 0.0f};
+        if (a.temporal) {
+            gs = a.tg[i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) tgr[c] = a.tg[(1 + c) * ps + i];
+        }
+        const unsigned smask = a.spatial ? (unsigned)a.tg[5 * ps + i] : 0u;
+        const int e1 = (int)threadIdx.x + NTHREADS;
+        const bool has1 = e1 < HN;
+        long long gi[2];
+        bool gin[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int idx = h == 0 ? (int)threadIdx.x : (has1 ? e1 : 0);
             const int gx = x0 + idx % HW - 1, gy = y0 + idx / HW - 1;
-            const bool in = gx >= 0 && gx < W && gy >= 0 && gy < H;
-            const long long gi = in ? (long long)gy * W + gx : 0;   // off-frame: read pixel 0, masked
-            float uv[N];
+            gin[h] = gx >= 0 && gx < W && gy >= 0 && gy < H;
+            gi[h] = gin[h] ? (long long)gy * W + gx : 0;
+        }
+        float uv0[N], uv1[N];
 #pragma unroll
-            for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + gi];
+        for (int v = 0; v < N; ++v) {
+            uv0[v] = a.u[v * ps + gi[0]];
+            uv1[v] = a.u[v * ps + gi[1]];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // every load issued before the first store
 #pragma unroll
-            for (int v = 0; v < N; ++v) Ul[v * HN + idx] = in ? uv[v] : 0.0f;
+        for (int v = 0; v < N; ++v) Ul[v * HN + threadIdx.x] = gin[0] ? uv0[v] : 0.0f;
+        if (has1) {
+#pragma unroll
+            for (int v = 0; v < N; ++v) Ul[v * HN + e1] = gin[1] ? uv1[v] : 0.0f;
         }
         __syncthreads();
-        const int x = x0 + lx, y = y0 + ly;
-        if (x < W && y < H) {
-            const long long i = (long long)y * W + x;
+        if (own_in) {
             const bool hv[4] = {x + 1 < W, y + 1 < H, x > 0, y > 0};
-            float r[3], T[K + 1], Iv[3];
+            float r[3], T[K + 1];
 #pragma unroll
             for (int c = 0; c < 3; ++c) r[c] = Ul[c * HN + li];
 #pragma unroll
             for (int k = 0; k <= K; ++k) T[k] = Ul[(3 + k) * HN + li];
-            load3(a.I, ps, i, Iv);
-            const int id = a.ids[i];
-            const float w = a.wsr[i];
             float R[3], S[3], e[3];
             refl_shading<K>(r, T, bs, R, S);
 #pragma unroll
@@ -643,11 +669,7 @@ __device__ __forceinline__ void gn_build_body(const Args& a, const Lc& lc, const
             float g[N], M[N];
             // consistency pairs: their count and the sum of the partners' r (temporal
             // partners from the previous frame, spatial ones from the staged tile)
-            float gs = a.temporal ? a.tg[i] : 0.0f;
-            float tgr[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) tgr[c] = a.temporal ? a.tg[(1 + c) * ps + i] : 0.0f;
-            if (a.spatial) spatial_partners(Ul, li, (unsigned)a.tg[5 * ps + i], gs, tgr);
+            if (a.spatial) spatial_partners(Ul, li, smask, gs, tgr);
             diag_unary<K>(R, S, T, w, gs, bs, L, M);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -1052,11 +1074,9 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
     double acc[K + 1];
 #pragma unroll
     for (int l = 0; l <= K; ++l) acc[l] = 0.0;
-    double B64[K][3];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) B64[k][c] = st.refine ? a.b64[3 * k + c] : 0.0;
+    // the FP64 colours are read where they are used (uniform loads, reissued per
+    // batch): held through the tile loop they would take 6K registers
+    const double* __restrict__ b64 = a.b64;
     const int rows = TYW * a.ppt;
     const int tile_px = TX * rows;
     for (int tile = tset.c0; tile < tset.c1; tile += tset.step) {
@@ -1070,18 +1090,19 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
             if (x < W && y < H) {
                 const long long i = (long long)y * W + x;
                 float uv[N], Iv[3];
-#pragma unroll
-                for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + i];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) Iv[c] = a.I[c * ps + i];
                 if (st.add_delta) {
-                    // every load ahead of the u stores, which the compiler may not move them past
+                    // every load of the pixel in one batch, ahead of the u stores, which
+                    // the compiler may not move them past
                     float xv[N], pv[N];
 #pragma unroll
                     for (int v = 0; v < N; ++v) {
+                        uv[v] = a.u[v * ps + i];
                         xv[v] = a.delta[v * ps + i];
                         pv[v] = plast[v * ps + i];
                     }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Iv[c] = a.I[c * ps + i];
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int v = 0; v < N; ++v) xv[v] = xstored ? xv[v] : 0.0f;
 #pragma unroll
@@ -1090,6 +1111,11 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
                         uv[v] = uv[v] + x;
                         a.u[v * ps + i] = uv[v];
                     }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < N; ++v) uv[v] = a.u[v * ps + i];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) Iv[c] = a.I[c * ps + i];
                 }
                 if (st.refine) {
 #pragma unroll
@@ -1097,7 +1123,7 @@ __device__ __forceinline__ void apply_bsum_body(const Args& a, const Lc& lc, con
                         const double R = exp((double)uv[c]);
                         double S = (double)uv[3];
 #pragma unroll
-                        for (int k = 0; k < K; ++k) S += B64[k][c] * (double)uv[4 + k];
+                        for (int k = 0; k < K; ++k) S += b64[3 * k + c] * (double)uv[4 + k];
                         Rs[c][sp] = R;
                         Es[c][sp] = (double)Iv[c] - R * S;
                     }

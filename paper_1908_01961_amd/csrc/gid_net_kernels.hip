@@ -86,6 +86,16 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(ConvArgs a) {
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) bw[t][nb] = load8(a.w + ((t * C + nb * 16 + r16) * C + 8 * kq));
+    // masked gradient: the ReLU mask of the pixel this lane stores in the epilogue,
+    // loaded now as four 16-byte loads (its latency hides behind the MFMAs)
+    bf16x8 mk[4];
+    if constexpr (MODE == M_MASK) {
+        const int xp = x0 + lane;
+        const bool in = rowin && xp < W;
+        const long long px = in ? (long long)y * W + xp : 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mk[q] = in ? load8(a.mask + px * C + 8 * q) : zero8();
+    }
     float pool[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) pool[nb] = 0.0f;
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(ConvArgs a) {
                         r = (__bf16)g;
                     } else {
                         const float sv = v + (a.addc ? a.addc[o] : 0.0f);
-                        r = (__bf16)((in && (float)a.mask[px * C + o] > 0.0f) ? sv : 0.0f);
+                        r = (__bf16)(in ? sv : 0.0f);   // masked below, per stored pixel
                     }
                     blk[lp * C + o] = r;
                 }
@@ -152,9 +162,15 @@ __global__ __launch_bounds__(CONV_THREADS) void k_conv(ConvArgs a) {
         if (rowin && xp < W) {
             const long long px = (long long)y * W + xp;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                *reinterpret_cast<bf16x8*>(a.out_b + px * C + 8 * q) =
-                    *reinterpret_cast<const bf16x8*>(blk + lane * C + 8 * q);
+            for (int q = 0; q < 4; ++q) {
+                bf16x8 v = *reinterpret_cast<const bf16x8*>(blk + lane * C + 8 * q);
+                if constexpr (MODE == M_MASK) {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (!((float)mk[q][j] > 0.0f)) v[j] = (__bf16)0.0f;
+                }
+                *reinterpret_cast<bf16x8*>(a.out_b + px * C + 8 * q) = v;
+            }
         }
     } else {
 #pragma unroll
