@@ -1258,44 +1258,44 @@ constexpr int BSOLVE_THREADS = 512;
 
 // One workgroup: reduce the per-workgroup sums, assemble the 3K x 3K system of
 // the base-colour step, solve it by FP64 Cholesky, apply the guards, update b.
+// The base-colour sums from the apply pass's per-workgroup partials, one sum per
+// wavefront (four per workgroup; workgroup g of a clip takes sums 4g .. 4g + 3):
+// every partial of a sum in one unrolled batch of masked loads (nb <= NB_BS_MAX =
+// 64 NCH), then the wavefront butterfly, so each sum is reduced in a fixed order.
+// The totals (times lambda_data) go to a.bsum, where the solve reads them.
+constexpr int BSR_WAVES = NTHREADS / 64;
+template <int K> constexpr int bsum_groups() { return (3 * K * (K + 1) / 2 + 3 * K + BSR_WAVES - 1) / BSR_WAVES; }
+
+template <int K>
+__device__ __forceinline__ void bsum_reduce_body(const Args& a, int g) {
+    constexpr int NS = 3 * K * (K + 1) / 2 + 3 * K;
+    constexpr int NCH = NB_BS_MAX / 64;
+    if (frame_idle(a)) return;
+    const int lane = threadIdx.x & 63, e = g * BSR_WAVES + (int)(threadIdx.x >> 6);
+    if (e >= NS) return;
+    const int nb = a.nb_bs;
+    const double* row = a.partials + (long long)R_BS * a.part_stride + (long long)e * nb;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) s += masked_load(row, lane + 64 * j, nb);
+    const double t = wave_sum(s);
+    if (lane == 0) a.bsum[e] = t * (double)a.lam.data;
+}
+
 template <int K>
 __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const Step& st, char* smem) {
     constexpr int NA = 3 * K * (K + 1) / 2;
     constexpr int NS = NA + 3 * K;
     constexpr int NN = 3 * K;
-    const int nb = a.nb_bs;
     double* sums = reinterpret_cast<double*>(smem);
     double (*Hm)[NN + 1] = reinterpret_cast<double (*)[NN + 1]>(smem + 8 * NS);
     double* gv = reinterpret_cast<double*>(smem + 8 * (NS + NN * (NN + 1)));
     if (frame_idle(a)) return;
-    const double* part = a.partials + (long long)R_BS * a.part_stride;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-    // U sums per wavefront per round, every partial of a sum in one unrolled batch
-    // (nb <= NB_BS_MAX = 64 NCH), so each lane has U NCH independent loads in flight
-    constexpr int U = K <= 9 ? 4 : 2;
-    constexpr int NCH = NB_BS_MAX / 64;
-    for (int e0 = wave; e0 < NS; e0 += nw * U) {
-        double s[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            s[u] = 0.0;
-            const int e = e0 + u * nw;
-            const double* row = part + (long long)(e < NS ? e : NS - 1) * nb;
-#pragma unroll
-            for (int j = 0; j < NCH; ++j) s[u] += masked_load(row, lane + 64 * j, nb);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double t = wave_sum(s[u]);
-            const int e = e0 + u * nw;
-            if (lane == 0 && e < NS) sums[e] = t * (double)a.lam.data;
-        }
-    }
+    // the sums, reduced from the apply pass's partials by the reduction kernel
+    // launched just before (many workgroups while this one solves)
+    for (int e = threadIdx.x; e < NS; e += blockDim.x) sums[e] = a.bsum[e];
     __syncthreads();
-    if (st.debug) {   // publish the raw sums for single-step access
-        for (int e = threadIdx.x; e < NS; e += blockDim.x) a.bsum[e] = sums[e];
-        return;
-    }
+    if (st.debug) return;   // the raw sums stay published for single-step access
     const double npix = a.bstep_sum ? 1.0 : (double)a.W * (double)a.H;
     const double lir = a.lam.ir, lcr = a.lam.cr;
     for (int e = threadIdx.x; e < NN * NN; e += blockDim.x) {
@@ -1347,7 +1347,8 @@ __device__ __forceinline__ void bsolve_body(const Args& a, const Lc& lc, const S
     // H = L L^T and the two triangular solves on one wavefront, in registers:
     // lane i holds row i of H (then of L) and entry i of the right-hand side;
     // column values travel by readlane, so no step waits on LDS.
-    if (threadIdx.x >= 64) return;        // lane == threadIdx.x from here on
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
     const bool act = lane < NN;
     double h[NN];
 #pragma unroll
@@ -1677,6 +1678,17 @@ __global__ __launch_bounds__(NTHREADS) void kb_scan(const BatchArgs ba, Step st)
     scan_body(ba.a[c], clip_grid(ba.wg_pix, c), st, smem);
 }
 
+template <int K>
+__global__ __launch_bounds__(NTHREADS) void k_bsum_reduce(Args a, Step st) {
+    bsum_reduce_body<K>(a, (int)blockIdx.x);
+}
+// bsum_groups<KB>() workgroups per clip
+template <int KB>
+__global__ __launch_bounds__(NTHREADS) void kb_bsum_reduce(const BatchArgs ba, Step st) {
+    constexpr int G = bsum_groups<KB>();
+    bsum_reduce_body<KB>(ba.a[blockIdx.x / G], (int)(blockIdx.x % G));
+}
+
 // one workgroup per clip
 template <int K>
 __global__ __launch_bounds__(BSOLVE_THREADS) void k_bsolve(Args a, Step st) {
@@ -1755,7 +1767,10 @@ hipError_t launch_kernel(Kern k, const Args& a, const Step& st, hipStream_t s) {
             case KN_APPLY_BSUM:
                 hipLaunchKernelGGL(k_apply_bsum<KK>, dim3(a.nb_bs), blk, lds_apply_bsum<KK>(), s, a, st);
                 break;
-            case KN_BSOLVE: hipLaunchKernelGGL(k_bsolve<KK>, dim3(1), dim3(BSOLVE_THREADS), lds_bsolve<KK>(), s, a, st); break;
+            case KN_BSOLVE:   // the sums' reduction, then the solve
+                hipLaunchKernelGGL(k_bsum_reduce<KK>, dim3(bsum_groups<KK>()), blk, 0, s, a, st);
+                hipLaunchKernelGGL(k_bsolve<KK>, dim3(1), dim3(BSOLVE_THREADS), lds_bsolve<KK>(), s, a, st);
+                break;
             case KN_ENERGY: hipLaunchKernelGGL(k_energy<KK>, grid, blk, LDS_SMALL, s, a, st); break;
             case KN_OUTPUT: hipLaunchKernelGGL(k_output<KK>, grid, blk, LDS_SMALL, s, a, st); break;
             default: break;
@@ -1794,6 +1809,7 @@ hipError_t launch_batch(Kern k, const BatchGrid& g, const Step& st, hipStream_t 
                 hipLaunchKernelGGL(kb_apply_bsum<KB>, gbs, blk, lds_apply_bsum<KB>(), s, g.ba, st);
                 break;
             case KN_BSOLVE:
+                hipLaunchKernelGGL(kb_bsum_reduce<KB>, dim3(g.ba.n * bsum_groups<KB>()), blk, 0, s, g.ba, st);
                 hipLaunchKernelGGL(kb_bsolve<KB>, gone, dim3(BSOLVE_THREADS), lds_bsolve<KB>(), s, g.ba, st);
                 break;
             case KN_ENERGY:
