@@ -211,7 +211,7 @@ def train_network(video, train_frames, w):
                                   supersample=w["supersample"])
     net_t = G.Net(K, tw, th)
     net_t.set_params(WSP.init_params(K, 1))
-    hist = WSP.train(net_t, store, epochs=4, lr=1e-3)
+    hist = WSP.train(net_t, store, epochs=12, lr=4e-4)
     del store
     net = WSP.transfer(net_t, K, W_, H_)
     net_t.close()
@@ -243,9 +243,14 @@ def bench_video(args, clip, workload, learned=True):
     targets = E_plain * (1.0 + 1e-4)
 
     def run(Pl, with_net, steps, warmup):
-        # at most twice the plain schedule's PCG iterations per frame
+        # at most twice the plain schedule's PCG iterations per frame; the energy is
+        # checked from one outer iteration before the plain schedule's PCG budget
+        # is spent (G P / Pl iterations), earlier checks being wasted on frames
+        # that cannot have met the target yet
         max_gn = -(-2 * w["G"] * w["P"] // Pl)
+        first_gn = max(1, (w["G"] * w["P"]) // Pl - 1)
         sl = video.solver(max_gn, Pl)
+        sl.set_energy_check_from(first_gn)
         if with_net:
             sl.set_warmstart(net)
         t, last = video.timed(sl, steps, warmup, targets, max_gn)
@@ -253,7 +258,7 @@ def bench_video(args, clip, workload, learned=True):
         E_l = np.array([e for e, _, _ in last])
         gn = np.array([g for _, g, _ in last])
         ex = E_l / E_plain - 1.0
-        d = dict(pcg_iters=Pl, max_gn=max_gn, mpx_s=round(video.px / t / 1e6, 2),
+        d = dict(pcg_iters=Pl, max_gn=max_gn, first_check=first_gn, mpx_s=round(video.px / t / 1e6, 2),
                  frames_s=round((video.F - 1) / t, 1), gn_mean=round(float(gn.mean()), 3), gn_max=int(gn.max()),
                  gn_histogram={int(g): int((gn == g).sum()) for g in np.unique(gn)},
                  energy_excess_max=float(ex.max()), energy_excess_median=float(np.median(ex)),
@@ -368,7 +373,7 @@ def main() -> int:
     ap.add_argument("--workload", default="video_1920x1080_k10")
     ap.add_argument("--frames", type=int, default=None, help="frames per clip (default: the workload's)")
     ap.add_argument("--learned", choices=("on", "off"), default="on")
-    ap.add_argument("--train-frames", type=int, default=2000, help="training pairs for the learned warm start")
+    ap.add_argument("--train-frames", type=int, default=3000, help="training pairs for the learned warm start")
     ap.add_argument("--extras", choices=("on", "off", "batch"), default="on",
                     help="also the 640x480 and 1280x720 plain lines and the 16-clip batch (batch: the batch only)")
     ap.add_argument("--cpu", choices=("on", "off"), default="on", help="time the FP64 oracle on the host")

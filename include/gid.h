@@ -170,6 +170,15 @@ gid_status gid_synchronize(gid_ctx *ctx);
  * GID_ERR_STATE (a frame is pending). */
 gid_status gid_set_energy_target(gid_ctx *ctx, double target, int32_t max_gn);
 
+/* In energy-target mode, evaluate and check the energy only after outer
+ * iterations first_gn, first_gn + 1, ... (and always after the last; default 1),
+ * for callers that know no frame meets its target earlier: the frame runs at
+ * least first_gn outer iterations and saves the earlier evaluations; the
+ * energy_half entries of unchecked iterations are NaN.  Applies to every
+ * following frame.  Errors: GID_ERR_INVALID_ARG (first_gn outside 1..64),
+ * GID_ERR_STATE (a frame is pending). */
+gid_status gid_set_energy_check_from(gid_ctx *ctx, int32_t first_gn);
+
 /* ---- single-step access (each step of the schedule on the current frame) ----
  * These run one step of the hot path on the frame loaded by gid_load_frame and
  * the state set by gid_set_state, so that each step can be checked on its own. */

@@ -71,6 +71,8 @@ struct gid_ctx {
     // iterations and stops the frame on the device once E <= target
     double target = 0.0;
     int target_gn = 0;
+    int target_first = 1;          // first outer iteration whose energy is checked (1-based)
+    int pend_first = 1;
     double* h_target = nullptr;    // pinned slot the target is uploaded from
     // replayable schedules keyed by (refine, temporal, record, energy target)
     hipGraphExec_t graphs[16] = {};
@@ -296,9 +298,11 @@ bool colours_valid(const double* b, int nk) {
 // and for batches.  Returns the number of energy slots used.
 // With check (energy-target mode) the energy is evaluated after every outer
 // iteration into slot g and compared with the frame's target on the device.
+// Checks start after outer iteration first (1-based; the last iteration is
+// always checked).
 template <typename LaunchFn>
 hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& launch, int* nslots,
-                            bool check = false) {
+                            bool check = false, int first = 1) {
     int slot = 0;
     hipError_t e = hipSuccess;
     if (check) record = false;
@@ -328,7 +332,7 @@ hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& l
                 if ((e = launch(KN_ENERGY_FINISH, s)) != hipSuccess) return e;
             }
         }
-        if (check) {
+        if (check && (g + 1 >= first || g == G - 1)) {
             s.slot = g;
             s.check = 1;
             if ((e = launch(KN_ENERGY, s)) != hipSuccess) return e;
@@ -352,7 +356,8 @@ hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& l
 hipError_t enqueue_outer(gid_ctx* c, hipStream_t st, const Args& base, bool refine, bool record, int* nslots) {
     const bool check = c->target > 0.0;
     return enqueue_schedule(check ? c->target_gn : c->prm.gn_iters, c->prm.pcg_iters, refine, record,
-                            [&](Kern k, const Step& s) { return L1(c, st, k, base, s); }, nslots, check);
+                            [&](Kern k, const Step& s) { return L1(c, st, k, base, s); }, nslots, check,
+                            c->target_first);
 }
 
 // Capture a schedule into a graph on a private stream (the caller's may be the
@@ -702,6 +707,7 @@ gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* id
     c->pend_stats = stats;
     c->pend_nhalf = nslots;
     c->pend_target = c->target > 0.0;
+    c->pend_first = c->target_first;
     c->pend_final_slot = (record && !c->pend_target) ? nslots - 1 : FINAL_SLOT;
     c->pend_frame = c->frame_index;
     c->pend_gn = c->prm.gn_iters;
@@ -730,6 +736,21 @@ gid_status gid_set_energy_target(gid_ctx* c, double target, int32_t max_gn) {
     return GID_OK;
 }
 
+gid_status gid_set_energy_check_from(gid_ctx* c, int32_t first_gn) {
+    if (!c) return GID_ERR_INVALID_ARG;
+    if (first_gn < 1 || first_gn > 64) return fail(c, GID_ERR_INVALID_ARG, "first_gn must be in 1..64");
+    if (c->pending) return fail(c, GID_ERR_STATE, "the previous frame is pending: call gid_synchronize first");
+    if (first_gn != c->target_first) {   // the target-mode schedule is captured for one first check
+        for (int k = 8; k < 16; ++k)
+            if (c->graphs[k]) {
+                (void)hipGraphExecDestroy(c->graphs[k]);
+                c->graphs[k] = nullptr;
+            }
+    }
+    c->target_first = first_gn;
+    return GID_OK;
+}
+
 gid_status gid_synchronize(gid_ctx* c) {
     if (!c) return GID_ERR_INVALID_ARG;
     GID_HIP(c, hipStreamSynchronize(c->stream));
@@ -752,8 +773,10 @@ gid_status gid_synchronize(gid_ctx* c) {
         for (int v = 0; v < NTERMS; ++v) st->energy_terms[v] = fin[1 + v];
         const int gn_done = c->pend_target ? (int)c->h_scal[S_GN_DONE] : c->pend_gn;
         st->n_half = c->pend_target ? gn_done : c->pend_nhalf;
-        for (int h = 0; h < st->n_half && h < GID_MAX_HALF_STEPS; ++h)
-            st->energy_half[h] = c->h_elog[(long long)h * ELOG_STRIDE];
+        for (int h = 0; h < st->n_half && h < GID_MAX_HALF_STEPS; ++h)   // unchecked iterations: NaN
+            st->energy_half[h] = (c->pend_target && h + 1 < c->pend_first && h + 1 < gn_done)
+                                     ? std::nan("")
+                                     : c->h_elog[(long long)h * ELOG_STRIDE];
         for (int g = 0; g < 64; ++g) st->pcg_rz_last[g] = c->h_scal[S_RZ_LOG + g];
         st->gn_done = gn_done;
         st->pcg_breakdowns = (int32_t)c->h_scal[S_BREAKDOWNS];

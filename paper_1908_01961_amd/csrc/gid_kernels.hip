@@ -1557,7 +1557,7 @@ __device__ __forceinline__ void energy_finish_body(const Args& a, const Lc& lc, 
             // also the frame's final energy unless a later iteration runs
             double* fin = a.elog + (long long)ELOG_FINAL_SLOT * ELOG_STRIDE;
             for (int v = 0; v <= NTERMS; ++v) fin[v] = slot[v];
-            a.scal[S_GN_DONE] += 1.0;
+            a.scal[S_GN_DONE] = (double)(st.gn + 1);   // outer iterations run so far
             if (s <= a.scal[S_TARGET]) a.scal[S_DONE] = 1.0;
         }
     }

@@ -74,6 +74,7 @@ SIGNATURES = [
                                       POINTER(GidFrameStats)]),
     ("gid_synchronize", c_int32, [c_void_p]),
     ("gid_set_energy_target", c_int32, [c_void_p, c_double, c_int32]),
+    ("gid_set_energy_check_from", c_int32, [c_void_p, c_int32]),
     ("gid_load_frame", c_int32, [c_void_p, c_void_p, c_void_p]),
     ("gid_set_state", c_int32, [c_void_p, c_void_p, POINTER(c_double)]),
     ("gid_set_prev_frame", c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -329,6 +330,10 @@ class Solver:
         """Stop each following frame once its energy is <= target (up to max_gn
         outer iterations); target <= 0 restores the fixed schedule."""
         self._check(self.lib.gid_set_energy_target(self.h, float(target), int(max_gn)), "gid_set_energy_target")
+
+    def set_energy_check_from(self, first_gn: int):
+        """Check the energy target only after outer iteration first_gn (1-based) and later."""
+        self._check(self.lib.gid_set_energy_check_from(self.h, int(first_gn)), "gid_set_energy_check_from")
 
     def decompose_frame(self, frame, ids, layers=None):
         self.decompose_frame_async(frame, ids, layers)

@@ -40,11 +40,13 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _run(torch, c, G_, nframes, target=None, max_gn=0, use_graph=1):
+def _run(torch, c, G_, nframes, target=None, max_gn=0, use_graph=1, first_gn=None):
     import paper_1908_01961_amd as G
     s = G.Solver(c.width, c.height, G.default_params(c.K, gn_iters=G_, pcg_iters=8, temporal=1,
                                                      record_energy=0, use_graph=use_graph))
     s.set_base_colors(c.b_init)
+    if first_gn is not None:
+        s.set_energy_check_from(first_gn)
     out = []
     layers = torch.empty((c.K + 4, c.height, c.width), dtype=torch.float32, device="cuda")
     for t in range(nframes):
@@ -128,4 +130,45 @@ def test_second_frame_before_synchronize_is_refused(torch):
     assert e.value.status == 4
     _, st = s.decompose_frame(_dev(torch, c.frames[1]), _dev(torch, c.ids[1]))
     assert st["frame_index"] == 1 and np.isfinite(st["energy_final"])
+    s.close()
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_checks_from_a_later_iteration(torch, graph):
+    """Checks from outer iteration 3: an always-met target stops after iteration 3
+    (the fixed 3-iteration schedule bit for bit, energies of iterations 1-2 NaN);
+    with max_gn 2 below the first check the last iteration is still checked; an
+    unreachable target runs max_gn as before."""
+    _say("checks from iteration 3, 160x120 K=6, 2 frames, graph", graph)
+    c = make_clip(160, 120, 6, 2, 203)
+    three = _run(torch, c, 3, 2, use_graph=graph)
+    two = _run(torch, c, 2, 2, use_graph=graph)
+    met = _run(torch, c, 3, 2, target=1e300, max_gn=5, use_graph=graph, first_gn=3)
+    short = _run(torch, c, 3, 2, target=1e300, max_gn=2, use_graph=graph, first_gn=3)
+    never = _run(torch, c, 3, 2, target=1e-300, max_gn=4, use_graph=graph, first_gn=3)
+    four = _run(torch, c, 4, 2, use_graph=graph)
+    for f3, f2, f4, m, sh, nv in zip(three, two, four, met, short, never):
+        assert m["stats"]["gn_done"] == 3
+        assert np.array_equal(f3["layers"], m["layers"]) and np.array_equal(f3["b"], m["b"])
+        assert m["stats"]["energy_final"] == f3["stats"]["energy_final"]
+        eh = m["stats"]["energy_half"]
+        assert len(eh) == 3 and np.isnan(eh[0]) and np.isnan(eh[1]) and eh[2] == f3["stats"]["energy_final"]
+        assert sh["stats"]["gn_done"] == 2
+        assert np.array_equal(f2["layers"], sh["layers"])
+        assert sh["stats"]["energy_final"] == f2["stats"]["energy_final"]
+        assert not np.isnan(sh["stats"]["energy_half"][-1])
+        assert nv["stats"]["gn_done"] == 4
+        assert np.array_equal(f4["layers"], nv["layers"])
+        assert nv["stats"]["energy_final"] == f4["stats"]["energy_final"]
+
+
+def test_check_from_refuses_bad_values(torch):
+    import paper_1908_01961_amd as G
+    c = make_clip(64, 48, 4, 1, 204)
+    s = G.Solver(c.width, c.height, G.default_params(c.K))
+    for bad in (0, 65):
+        with pytest.raises(G.GidError) as e:
+            s.set_energy_check_from(bad)
+        assert e.value.status == 1
+    s.set_energy_check_from(2)
     s.close()
