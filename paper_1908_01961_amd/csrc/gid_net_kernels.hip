@@ -56,170 +56,210 @@ __device__ __forceinline__ double wave_sum64(double v) {
 
 // ------------------------------------------------------------ convolution
 
-// The workgroup's four rows (one per wavefront) read a 6-row x 66-pixel halo
-// tile of the input, staged once in LDS with coalesced 16-byte loads; every
+// A tile's four rows (one per wavefront) read a 6-row x 66-pixel halo tile of
+// the input, staged in LDS with coalesced 16-byte loads; every
 // A fragment is then one conflict-free 128-bit LDS read (16 lanes cover 16
 // consecutive pixels = 1 KiB).  MODE selects the epilogue at compile time.
 constexpr int TROWS = CONV_ROWS + 2, TCOLS = STRIP + 2;
 
+// Staged 16-byte elements of one tile, and per thread.
+constexpr int NSE = TROWS * TCOLS * 4;
+constexpr int SPT = (NSE + CONV_THREADS - 1) / CONV_THREADS;
+
+// Issue the loads of tile t's staged input (off-frame elements are zero).
+__device__ __forceinline__ void conv_stage_load(const ConvArgs& a, int t, int nsx, bf16x8* stg) {
+    const int y0 = (t / nsx) * CONV_ROWS, x0 = (t % nsx) * STRIP;
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int e = (int)threadIdx.x + j * CONV_THREADS;
+        const int q = e & 3, col = (e >> 2) % TCOLS, row = (e >> 2) / TCOLS;
+        const int yy = y0 + row - 1, xx = x0 + col - 1;
+        stg[j] = (e < NSE && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                     ? load8(a.in + ((long long)yy * a.W + xx) * C + 8 * q)
+                     : zero8();
+    }
+}
+
+__device__ __forceinline__ void conv_stage_store(__bf16 (*buf)[TCOLS][C], const bf16x8* stg) {
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int e = (int)threadIdx.x + j * CONV_THREADS;
+        if (e >= NSE) continue;
+        const int q = e & 3, col = (e >> 2) % TCOLS, row = (e >> 2) / TCOLS;
+        *reinterpret_cast<bf16x8*>(&buf[row][col][8 * q]) = stg[j];
+    }
+}
+
+// A resident workgroup takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... and
+// double-buffers their staged input: the next tile's loads are in flight while
+// the current tile's MFMAs and epilogue run.  The weights are loaded once.
+// Every tile's arithmetic and partial sums are those of one workgroup per tile.
 template <int NB, int MODE>
 __global__ __launch_bounds__(CONV_THREADS) void k_conv(ConvArgs a) {
-    __shared__ __align__(16) __bf16 tile[TROWS][TCOLS][C];
+    __shared__ __align__(16) __bf16 tiles[2][TROWS][TCOLS][C];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r16 = lane & 15, kq = lane >> 4;
     const int W = a.W, H = a.H;
     const int nsx = (W + STRIP - 1) / STRIP;
-    const long long wave_id = (long long)blockIdx.x * CONV_ROWS + wv;
-    const int y0 = ((int)blockIdx.x / nsx) * CONV_ROWS, x0 = ((int)blockIdx.x % nsx) * STRIP;
-    const int y = y0 + wv;
-    const bool rowin = y < H;
-    for (int e = threadIdx.x; e < TROWS * TCOLS * 4; e += CONV_THREADS) {
-        const int q = e & 3, col = (e >> 2) % TCOLS, row = (e >> 2) / TCOLS;
-        const int yy = y0 + row - 1, xx = x0 + col - 1;
-        const bf16x8 v = (yy >= 0 && yy < H && xx >= 0 && xx < W)
-                             ? load8(a.in + ((long long)yy * W + xx) * C + 8 * q)
-                             : zero8();
-        *reinterpret_cast<bf16x8*>(&tile[row][col][8 * q]) = v;
-    }
+    const int ntiles = nsx * ((H + CONV_ROWS - 1) / CONV_ROWS);
     bf16x8 bw[9][NB];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) bw[t][nb] = load8(a.w + ((t * C + nb * 16 + r16) * C + 8 * kq));
-    // masked gradient: the ReLU mask of the pixel this lane stores in the epilogue,
-    // loaded now as four 16-byte loads (its latency hides behind the MFMAs)
-    bf16x8 mk[4];
-    if constexpr (MODE == M_MASK) {
-        const int xp = x0 + lane;
-        const bool in = rowin && xp < W;
-        const long long px = in ? (long long)y * W + xp : 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) mk[q] = in ? load8(a.mask + px * C + 8 * q) : zero8();
+    bf16x8 stg[SPT];
+    int t = blockIdx.x;
+    if (t < ntiles) {
+        conv_stage_load(a, t, nsx, stg);
+        conv_stage_store(tiles[0], stg);
     }
-    float pool[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) pool[nb] = 0.0f;
-    double lacc = 0.0;
-    f32x4 acc[4][NB];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     __syncthreads();
+    for (int buf = 0; t < ntiles; t += gridDim.x, buf ^= 1) {
+        const int tn = t + (int)gridDim.x;
+        if (tn < ntiles) conv_stage_load(a, tn, nsx, stg);   // in flight through this tile
+        __bf16 (*tile)[TCOLS][C] = tiles[buf];
+        const long long wave_id = (long long)t * CONV_ROWS + wv;
+        const int y0 = (t / nsx) * CONV_ROWS, x0 = (t % nsx) * STRIP;
+        const int y = y0 + wv;
+        const bool rowin = y < H;
+        // masked gradient: the ReLU mask of the pixel this lane stores in the epilogue,
+        // loaded now as four 16-byte loads (its latency hides behind the MFMAs)
+        bf16x8 mk[4];
+        if constexpr (MODE == M_MASK) {
+            const int xp = x0 + lane;
+            const bool in = rowin && xp < W;
+            const long long px = in ? (long long)y * W + xp : 0;
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
+            for (int q = 0; q < 4; ++q) mk[q] = in ? load8(a.mask + px * C + 8 * q) : zero8();
+        }
+        float pool[NB];
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[wv + dy][16 * m + r16 + dx][8 * kq]);
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[dy * 3 + dx][nb], acc[m][nb], 0, 0, 0);
-            }
-    // epilogue: pixel x0 + 16 m + 4 kq + i, channel 16 nb + r16
-    constexpr bool NHWC_OUT = MODE == M_RELU || MODE == M_LOSS || MODE == M_MASK;
-    if constexpr (NHWC_OUT) {
-        // values to BF16 in this wavefront's 64 x 32 block of the (no longer needed)
-        // input tile, then each lane stores one pixel's 64 bytes with four 16-byte stores
-        static_assert(NB == 2, "pixel-major outputs carry all 32 channels");
-        __syncthreads();
-        __bf16* blk = &tile[0][0][0] + wv * STRIP * C;
+        for (int nb = 0; nb < NB; ++nb) pool[nb] = 0.0f;
+        double lacc = 0.0;
+        f32x4 acc[4][NB];
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int lp = 16 * m + 4 * kq + i, xp = x0 + lp;
-                const bool in = rowin && xp < W;
+            for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const bf16x8 av = *reinterpret_cast<const bf16x8*>(&tile[wv + dy][16 * m + r16 + dx][8 * kq]);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb)
+                        acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[dy * 3 + dx][nb], acc[m][nb], 0, 0, 0);
+                }
+        // epilogue: pixel x0 + 16 m + 4 kq + i, channel 16 nb + r16
+        constexpr bool NHWC_OUT = MODE == M_RELU || MODE == M_LOSS || MODE == M_MASK;
+        if constexpr (NHWC_OUT) {
+            // values to BF16 in this wavefront's 64 x 32 block of the (no longer needed)
+            // input tile, then each lane stores one pixel's 64 bytes with four 16-byte stores
+            static_assert(NB == 2, "pixel-major outputs carry all 32 channels");
+            __syncthreads();
+            __bf16* blk = &tile[0][0][0] + wv * STRIP * C;
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int lp = 16 * m + 4 * kq + i, xp = x0 + lp;
+                    const bool in = rowin && xp < W;
+                    const long long px = (long long)y * W + xp;
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const int o = 16 * nb + r16;
+                        const float v = acc[m][nb][i];
+                        __bf16 r;
+                        if constexpr (MODE == M_RELU) {
+                            r = (__bf16)fmaxf(v + a.bias[o], 0.0f);
+                            if (in) pool[nb] += (float)r;
+                        } else if constexpr (MODE == M_LOSS) {
+                            float g = 0.0f;
+                            if (in && o < a.nout) {
+                                const float e = (v + a.bias[o]) - a.tgt[o * a.ps + px];
+                                g = e * a.gscale;
+                                lacc += (double)e * (double)e;
+                            }
+                            r = (__bf16)g;
+                        } else {
+                            const float sv = v + (a.addc ? a.addc[o] : 0.0f);
+                            r = (__bf16)(in ? sv : 0.0f);   // masked below, per stored pixel
+                        }
+                        blk[lp * C + o] = r;
+                    }
+                }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int xp = x0 + lane;
+            if (rowin && xp < W) {
                 const long long px = (long long)y * W + xp;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    bf16x8 v = *reinterpret_cast<const bf16x8*>(blk + lane * C + 8 * q);
+                    if constexpr (MODE == M_MASK) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            if (!((float)mk[q][j] > 0.0f)) v[j] = (__bf16)0.0f;
+                    }
+                    *reinterpret_cast<bf16x8*>(a.out_b + px * C + 8 * q) = v;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     const int o = 16 * nb + r16;
-                    const float v = acc[m][nb][i];
-                    __bf16 r;
-                    if constexpr (MODE == M_RELU) {
-                        r = (__bf16)fmaxf(v + a.bias[o], 0.0f);
-                        if (in) pool[nb] += (float)r;
-                    } else if constexpr (MODE == M_LOSS) {
-                        float g = 0.0f;
-                        if (in && o < a.nout) {
-                            const float e = (v + a.bias[o]) - a.tgt[o * a.ps + px];
-                            g = e * a.gscale;
-                            lacc += (double)e * (double)e;
+                    const int xb = x0 + 16 * m + 4 * kq;
+                    if (!rowin) continue;
+                    const long long pb = (long long)y * W + xb;
+                    if constexpr (MODE == M_ADD) {
+                        if (o >= a.nout) continue;
+                        const float bo = a.bias[o];
+                        if ((W & 3) == 0 && xb + 3 < W) {
+                            const float4 up = *reinterpret_cast<const float4*>(a.uprev + o * a.ps + pb);
+                            float4 r;
+                            r.x = up.x + (acc[m][nb][0] + bo);
+                            r.y = up.y + (acc[m][nb][1] + bo);
+                            r.z = up.z + (acc[m][nb][2] + bo);
+                            r.w = up.w + (acc[m][nb][3] + bo);
+                            *reinterpret_cast<float4*>(a.out_f + o * a.ps + pb) = r;
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (xb + i < W) a.out_f[o * a.ps + pb + i] = a.uprev[o * a.ps + pb + i] + (acc[m][nb][i] + bo);
                         }
-                        r = (__bf16)g;
-                    } else {
-                        const float sv = v + (a.addc ? a.addc[o] : 0.0f);
-                        r = (__bf16)(in ? sv : 0.0f);   // masked below, per stored pixel
-                    }
-                    blk[lp * C + o] = r;
-                }
-            }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int xp = x0 + lane;
-        if (rowin && xp < W) {
-            const long long px = (long long)y * W + xp;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                bf16x8 v = *reinterpret_cast<const bf16x8*>(blk + lane * C + 8 * q);
-                if constexpr (MODE == M_MASK) {
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        if (!((float)mk[q][j] > 0.0f)) v[j] = (__bf16)0.0f;
-                }
-                *reinterpret_cast<bf16x8*>(a.out_b + px * C + 8 * q) = v;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const int o = 16 * nb + r16;
-                const int xb = x0 + 16 * m + 4 * kq;
-                if (!rowin) continue;
-                const long long pb = (long long)y * W + xb;
-                if constexpr (MODE == M_ADD) {
-                    if (o >= a.nout) continue;
-                    const float bo = a.bias[o];
-                    if ((W & 3) == 0 && xb + 3 < W) {
-                        const float4 up = *reinterpret_cast<const float4*>(a.uprev + o * a.ps + pb);
-                        float4 r;
-                        r.x = up.x + (acc[m][nb][0] + bo);
-                        r.y = up.y + (acc[m][nb][1] + bo);
-                        r.z = up.z + (acc[m][nb][2] + bo);
-                        r.w = up.w + (acc[m][nb][3] + bo);
-                        *reinterpret_cast<float4*>(a.out_f + o * a.ps + pb) = r;
                     } else {
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
-                            if (xb + i < W) a.out_f[o * a.ps + pb + i] = a.uprev[o * a.ps + pb + i] + (acc[m][nb][i] + bo);
+                            if (xb + i < W) a.out_f[(pb + i) * C + o] = acc[m][nb][i] + a.bias[o];
                     }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (xb + i < W) a.out_f[(pb + i) * C + o] = acc[m][nb][i] + a.bias[o];
                 }
             }
         }
-    }
-    if constexpr (MODE == M_RELU) {
-        if (a.pool_part) {
+        if constexpr (MODE == M_RELU) {
+            if (a.pool_part) {
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const float s = col_sum(pool[nb]);
-                if (kq == 0) a.pool_part[wave_id * C + 16 * nb + r16] = s;
+                for (int nb = 0; nb < NB; ++nb) {
+                    const float s = col_sum(pool[nb]);
+                    if (kq == 0) a.pool_part[wave_id * C + 16 * nb + r16] = s;
+                }
+                if (NB == 1 && kq == 0) a.pool_part[wave_id * C + 16 + r16] = 0.0f;
             }
-            if (NB == 1 && kq == 0) a.pool_part[wave_id * C + 16 + r16] = 0.0f;
         }
-    }
-    if constexpr (MODE == M_LOSS) {
-        if (a.loss_part) {
-            const double s = wave_sum64(lacc);
-            if (lane == 0) a.loss_part[wave_id] = s;
+        if constexpr (MODE == M_LOSS) {
+            if (a.loss_part) {
+                const double s = wave_sum64(lacc);
+                if (lane == 0) a.loss_part[wave_id] = s;
+            }
         }
+        // the next tile's input into the other buffer (last read before the previous
+        // barrier); the barrier also ends this tile's use of its buffer
+        if (tn < ntiles) conv_stage_store(tiles[buf ^ 1], stg);
+        __syncthreads();
     }
 }
 
@@ -421,21 +461,39 @@ __global__ __launch_bounds__(HEAD_THREADS) void k_loss_total(const double* loss_
 
 // Network input: the frame (3 planes) and the previous unknowns (n planes),
 // rounded to BF16, zero channels up to 32.
-__global__ void k_pack_input(const float* frame, const float* u, int n, long long ps, __bf16* out) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ps * 4) return;
-    const long long px = e >> 2;
-    const int q = (int)(e & 3);
-    bf16x8 v;
+// One workgroup per 256 pixels: every channel plane is read with coalesced loads, each
+// thread packs its pixel's 32 BF16 channels into LDS, and the workgroup's 16 KiB block
+// is written out with contiguous 16-byte stores.
+constexpr int PACK_PX = 256;
+
+__global__ __launch_bounds__(PACK_PX) void k_pack_input(const float* frame, const float* u, int n, long long ps,
+                                                        __bf16* out) {
+    __shared__ __align__(16) __bf16 blk[PACK_PX][C];
+    const long long p0 = (long long)blockIdx.x * PACK_PX;
+    const long long px = p0 + threadIdx.x;
+    const bool in = px < ps;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int ch = 8 * q + j;
-        float f = 0.0f;
-        if (ch < 3) f = frame[ch * ps + px];
-        else if (ch < 3 + n) f = u[(ch - 3) * ps + px];
-        v[j] = (__bf16)f;
+    for (int q = 0; q < 4; ++q) {
+        bf16x8 v;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int ch = 8 * q + j;
+            float f = 0.0f;
+            if (in && ch < 3) f = frame[ch * ps + px];
+            else if (in && ch < 3 + n) f = u[(ch - 3) * ps + px];
+            v[j] = (__bf16)f;
+        }
+        *reinterpret_cast<bf16x8*>(&blk[threadIdx.x][8 * q]) = v;
     }
-    *reinterpret_cast<bf16x8*>(out + px * C + 8 * q) = v;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = (int)threadIdx.x + PACK_PX * j;
+        const long long pp = p0 + (e >> 2);
+        if (pp < ps)
+            *reinterpret_cast<bf16x8*>(out + pp * C + 8 * (e & 3)) =
+                *reinterpret_cast<const bf16x8*>(&blk[e >> 2][8 * (e & 3)]);
+    }
 }
 
 // BF16 copies of one layer's FP32 master weights for the forward pass
@@ -471,14 +529,34 @@ __global__ void k_adam(float* p, float* m, float* v, const float* g, long long n
 
 // ------------------------------------------------------------ launchers
 
-// One workgroup per tile of 4 rows x 64 pixels (a persistent grid that loaded the weights once
-// per resident workgroup was measured slower).
+// Tiles of 4 rows x 64 pixels; one partial slot per wavefront of each tile.
 int conv_grid(int W, int H) {
     return ((W + STRIP - 1) / STRIP) * ((H + CONV_ROWS - 1) / CONV_ROWS);
 }
 
+// Resident workgroups per compute unit of the convolution (two 6 x 66 x 32 BF16 tiles,
+// 50.7 KB of LDS each, so three fit in 160 KB).
+#ifndef CONV_WG_PER_CU
+#define CONV_WG_PER_CU 2
+#endif
+
+static int conv_resident() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 0;
+        cus[dev] = n;
+    }
+    return cus[dev] * CONV_WG_PER_CU;
+}
+
 hipError_t launch_conv(const ConvArgs& a, int nb, hipStream_t s) {
-    const dim3 grid(conv_grid(a.W, a.H)), blk(CONV_THREADS);
+    const int ntiles = conv_grid(a.W, a.H), res = conv_resident();
+    if (res <= 0) return hipErrorInvalidDevice;
+    if (ntiles <= 0) return hipSuccess;
+    const dim3 grid(ntiles < res ? ntiles : res), blk(CONV_THREADS);
     // one output block only where nothing reads channels 16..31 of the output
     if (nb == 1 && a.mode != M_ADD) return hipErrorInvalidValue;
     switch (a.mode) {
@@ -519,8 +597,8 @@ hipError_t launch_loss_total(const double* loss_part, long long nparts, double s
 }
 
 hipError_t launch_pack_input(const float* frame, const float* u, int n, long long ps, __bf16* out, hipStream_t s) {
-    const long long ne = ps * 4;
-    hipLaunchKernelGGL(k_pack_input, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, frame, u, n, ps, out);
+    hipLaunchKernelGGL(k_pack_input, dim3((unsigned)((ps + PACK_PX - 1) / PACK_PX)), dim3(PACK_PX), 0, s, frame, u, n,
+                       ps, out);
     return hipGetLastError();
 }
 
