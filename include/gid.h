@@ -387,6 +387,12 @@ gid_status gid_net_train_step(gid_net *net, const float *frame_dev, const float 
 gid_status gid_net_layer_forward(gid_net *net, int32_t layer, const void *in_dev, float *out_dev);
 gid_status gid_net_layer_wgrad(gid_net *net, int32_t layer, const void *x_dev, const void *gy_dev,
                                float *gw_host, float *gb_host);
+
+/* Launch shape of the convolutions: at most `workgroups` workgroups, each taking
+ * the 4 x 64-pixel tiles i, i + workgroups, ... in turn (0, the default: two per
+ * compute unit, the resident grid).  Every shape gives bit-identical results.
+ * Errors: GID_ERR_INVALID_ARG for a negative count. */
+gid_status gid_net_set_conv_workgroups(gid_net *net, int32_t workgroups);
 const char *gid_net_last_error(const gid_net *net);
 
 /* Attach a network as the warm start of a solver context (NULL detaches).  On

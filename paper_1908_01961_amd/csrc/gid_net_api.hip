@@ -36,6 +36,7 @@ struct gid_net {
     float* h_db = nullptr;
     double* h_loss = nullptr;
     int adam_t = 0;
+    int conv_wg = 0;         // convolution workgroups at most (0: the resident grid)
     void* arena = nullptr;
     std::string err;
 };
@@ -94,6 +95,7 @@ ConvArgs conv_args(const gid_net* net, int l, const __bf16* in, int mode) {
     a.ps = net->ps;
     a.mode = mode;
     a.nout = net->lcout[l];
+    a.max_wg = net->conv_wg;
     return a;
 }
 
@@ -196,6 +198,7 @@ hipError_t train_pass(gid_net* net, const float* frame, const float* u, const fl
         d.out_b = gx;
         d.mask = net->act[l];
         d.addc = (l == NCONV - 1) ? net->addc : nullptr;
+        d.max_wg = net->conv_wg;
         if ((e = launch_conv(d, 2, s)) != hipSuccess) return e;
         __bf16* t = gy;
         gy = gx;
@@ -396,6 +399,12 @@ gid_status gid_net_layer_wgrad(gid_net* net, int32_t layer, const void* x_dev, c
     NET_HIP(net, hipMemcpyAsync(gb_host, net->G + net->boff[layer], 4 * (size_t)net->lcout[layer],
                                 hipMemcpyDeviceToHost, net->stream));
     NET_HIP(net, hipStreamSynchronize(net->stream));
+    return GID_OK;
+}
+
+gid_status gid_net_set_conv_workgroups(gid_net* net, int32_t workgroups) {
+    if (!net || workgroups < 0) return nfail(net, GID_ERR_INVALID_ARG, "workgroups must be >= 0");
+    net->conv_wg = workgroups;
     return GID_OK;
 }
 

@@ -36,6 +36,7 @@ struct ConvArgs {
     const __bf16* mask;      // M_MASK: activation whose positive entries pass
     const float* addc;       // M_MASK: per-channel term added before the mask (may be null)
     float* pool_part;        // M_RELU: per-wavefront channel sums (may be null)
+    int max_wg;              // workgroups of the launch at most (0: the resident grid)
 };
 
 struct WgradArgs {

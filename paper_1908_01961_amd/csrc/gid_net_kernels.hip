@@ -553,7 +553,8 @@ static int conv_resident() {
 }
 
 hipError_t launch_conv(const ConvArgs& a, int nb, hipStream_t s) {
-    const int ntiles = conv_grid(a.W, a.H), res = conv_resident();
+    const int ntiles = conv_grid(a.W, a.H);
+    const int res = a.max_wg > 0 ? a.max_wg : conv_resident();
     if (res <= 0) return hipErrorInvalidDevice;
     if (ntiles <= 0) return hipSuccess;
     const dim3 grid(ntiles < res ? ntiles : res), blk(CONV_THREADS);

@@ -109,6 +109,7 @@ SIGNATURES = [
                                      POINTER(c_double)]),
     ("gid_net_layer_forward", c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     ("gid_net_layer_wgrad", c_int32, [c_void_p, c_int32, c_void_p, c_void_p, POINTER(c_float), POINTER(c_float)]),
+    ("gid_net_set_conv_workgroups", c_int32, [c_void_p, c_int32]),
     ("gid_net_last_error", ctypes.c_char_p, [c_void_p]),
     ("gid_set_warmstart", c_int32, [c_void_p, c_void_p]),
     ("gid_cluster_frame", c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,
@@ -543,6 +544,10 @@ class Net:
         self._check(self.lib.gid_net_layer_wgrad(self.h, int(layer), x, gy, gw.ctypes.data_as(POINTER(c_float)),
                                                  gb.ctypes.data_as(POINTER(c_float))), "gid_net_layer_wgrad")
         return gw.reshape(cout, cin, 3, 3), gb
+
+    def set_conv_workgroups(self, workgroups: int):
+        """At most this many convolution workgroups (0: the resident grid)."""
+        self._check(self.lib.gid_net_set_conv_workgroups(self.h, int(workgroups)), "gid_net_set_conv_workgroups")
 
 
 BATCH_LAUNCH = {"one": 0, "per_k": 1}

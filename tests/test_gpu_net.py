@@ -274,3 +274,87 @@ def test_training_reduces_the_loss(torch):
     _say(f"training: loss {losses[0]:.3e} -> {losses[-1]:.3e}")
     assert losses[-1] < 0.3 * losses[0]
     net.close()
+
+
+# -------------------------------------------------- many tiles per workgroup
+
+# 6 x 260 = 1560 tiles of 4 rows x 64 pixels (the last strip 54 pixels wide, the
+# last row group 3 rows high): more than the resident grid of two workgroups per
+# compute unit, so that each workgroup walks several tiles.
+BIG = dict(K=4, W=374, H=1039)
+
+
+def test_conv_launch_shapes_are_bit_identical(torch):
+    """The convolution's launch shape -- the resident grid (several tiles per
+    workgroup, the next tile's input staged while the current one computes), one
+    workgroup per tile, a single workgroup walking every tile, an odd count --
+    leaves the forward outputs, the gradients and the loss unchanged bit for bit:
+    a tile's arithmetic and its partial-sum slots do not depend on which
+    workgroup computes it."""
+    import paper_1908_01961_amd as G
+    K, W, H = BIG["K"], BIG["W"], BIG["H"]
+    ntiles = -(-W // 64) * -(-H // 4)
+    flat, _ = _random_params(K, 90)
+    frame, u = _inputs(K, W, H, 91)
+    rng = np.random.default_rng(92)
+    du_t = (0.05 * rng.normal(size=u.shape)).astype(np.float32)
+    db_t = (0.05 * rng.normal(size=3 * K)).astype(np.float32)
+    net = G.Net(K, W, H)
+    net.set_params(flat)
+    f, uu, t = _dev(torch, frame), _dev(torch, u), _dev(torch, du_t)
+    runs = {}
+    for wg in (0, ntiles, 1, 7):
+        net.set_conv_workgroups(wg)
+        uo = torch.empty((K + 4, H, W), dtype=torch.float32, device="cuda")
+        db = np.array(net.forward(f, uu, uo), np.float32)
+        g, loss = net.gradients(f, uu, t, db_t, 2.0)
+        runs[wg] = (uo.cpu().numpy(), db, np.array(g, np.float32), float(loss))
+        _say(f"conv workgroups {wg or 'resident'} of {ntiles} tiles: loss {loss:.10e}")
+    u0, db0, g0, l0 = runs[0]
+    assert np.isfinite(u0).all() and np.isfinite(g0).all()
+    for wg, (uw, dbw, gw, lw) in runs.items():
+        assert np.array_equal(uw, u0), wg
+        assert np.array_equal(dbw, db0), wg
+        assert np.array_equal(gw, g0), wg
+        assert lw == l0, wg
+    with pytest.raises(G.GidError):
+        net.set_conv_workgroups(-1)
+    net.close()
+
+
+def test_forward_at_full_size_matches_reference_on_sampled_pixels(torch):
+    """1920 x 1080, K = 10 (the warm start's size in the benchmark; the resident
+    grid walks 8100 tiles): du at sampled pixels against the oracle network
+    applied to the pixel's 13 x 13 neighbourhood, the receptive field of six 3 x 3
+    layers (clipped at the frame, where both sides pad with zeros).  Samples: the
+    frame's corners and edges, pixels on both sides of strip and row-group
+    boundaries, and random pixels."""
+    import paper_1908_01961_amd as G
+    K, W, H = 10, 1920, 1080
+    flat, p = _random_params(K, 95)
+    frame, u = _inputs(K, W, H, 96)
+    net = G.Net(K, W, H)
+    net.set_params(flat)
+    uo = torch.empty((K + 4, H, W), dtype=torch.float32, device="cuda")
+    net.forward(_dev(torch, frame), _dev(torch, u), uo)
+    got_all = uo.cpu().numpy()
+    net.close()
+    xs = [0, 1, 63, 64, 65, 127, 128, 959, 960, 1855, 1856, 1918, 1919]
+    ys = [0, 1, 3, 4, 5, 7, 8, 539, 540, 1075, 1076, 1078, 1079]
+    rng = np.random.default_rng(97)
+    pts = [(y, x) for y in ys for x in xs] + list(zip(rng.integers(0, H, 120).tolist(), rng.integers(0, W, 120).tolist()))
+    x_full = np.concatenate([frame, u]).astype(np.float64)
+    ref = np.empty((len(pts), K + 4))
+    got = np.empty((len(pts), K + 4))
+    for j, (y, x) in enumerate(pts):
+        y0, y1, x0, x1 = max(0, y - 6), min(H, y + 7), max(0, x - 6), min(W, x + 7)
+        d, _, _ = WS.forward(p, x_full[:, y0:y1, x0:x1])
+        ref[j] = d[:, y - y0, x - x0]
+        got[j] = got_all[:, y, x].astype(np.float64) - u[:, y, x]
+    # the whole-network bound of the 80 x 24 case, the RMS taken over the samples
+    step = 2.0 ** -8
+    bound = step * (np.abs(ref) + NLAYERS * np.sqrt((ref ** 2).mean()))
+    r = float((np.abs(got - ref) / bound).max())
+    _say(f"1920x1080 K=10 forward, {len(pts)} sampled pixels: max |du - ref| = {np.abs(got - ref).max():.2e} "
+         f"(max |ref| {np.abs(ref).max():.2e}); element error / one-BF16-step bound {r:.3f}")
+    assert r <= 1.0

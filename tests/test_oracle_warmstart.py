@@ -85,3 +85,30 @@ def test_adam_matches_torch():
         opt.step()
     for k in p:
         assert np.allclose(p[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_du_depends_only_on_the_13x13_neighbourhood():
+    """Six 3 x 3 layers: du at a pixel is the network applied to the pixel's
+    13 x 13 neighbourhood, clipped at the frame (zero padding on both sides), and
+    the one-pixel-smaller window does not give it.  The GPU test at full frame
+    size checks sampled pixels this way."""
+    rng = np.random.default_rng(5)
+    K, H, W = 2, 30, 40
+    n = K + 4
+    chans = [3 + n] + [WS.C_HID] * 5 + [n]
+    p = {}
+    for l in range(WS.N_CONV):
+        p[f"w{l}"] = rng.normal(0.0, np.sqrt(2.0 / (9 * chans[l])), size=(chans[l + 1], chans[l], 3, 3))
+        p[f"b{l}"] = rng.normal(0.0, 0.05, size=chans[l + 1])
+    p["hw"] = rng.normal(0.0, 0.2, size=(3 * K, WS.C_HID))
+    p["hb"] = rng.normal(0.0, 0.02, size=3 * K)
+    x = rng.uniform(-1.0, 1.0, size=(3 + n, H, W))
+    ident = lambda a: np.asarray(a, np.float64)   # noqa: E731
+    du, _, _ = WS.forward(p, x, rnd=ident)
+    for y, xx in [(0, 0), (0, 39), (29, 0), (29, 39), (3, 20), (15, 6), (15, 33), (14, 20), (22, 7)]:
+        y0, y1, x0, x1 = max(0, y - 6), min(H, y + 7), max(0, xx - 6), min(W, xx + 7)
+        d, _, _ = WS.forward(p, x[:, y0:y1, x0:x1], rnd=ident)
+        assert np.allclose(d[:, y - y0, xx - x0], du[:, y, xx], rtol=1e-12, atol=1e-12)
+    y, xx = 15, 20
+    d, _, _ = WS.forward(p, x[:, y - 5:y + 6, xx - 5:xx + 6], rnd=ident)
+    assert not np.allclose(d[:, 5, 5], du[:, y, xx], rtol=1e-6, atol=1e-9)
