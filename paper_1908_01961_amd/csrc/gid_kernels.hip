@@ -1646,6 +1646,12 @@ template <int K> constexpr int mv_waves() {
     return K <= 8 ? (lds_waves<K>() < cap ? lds_waves<K>() : cap) : 1;
 }
 #define GID_NO_ATTR(T)
+// energy: 170 VGPRs at K = 10 left two waves per SIMD, so the pixel grid's three
+// workgroups per CU ran in one and a half waves of workgroups; held to three waves
+// (168 VGPRs, no spills up to K = 10) it takes 73 us at 1920x1080 K = 10 (84 us
+// before).  Larger K keep the compiler's allocation.  The precompute is not held:
+// at three waves it spills from K = 8 on.
+#define GID_W3_ATTR(T) __attribute__((amdgpu_waves_per_eu((T) <= 10 ? 3 : 1)))
 #define GID_GN_ATTR(T) __attribute__((amdgpu_waves_per_eu(4)))
 #define GID_MV_ATTR(T) __attribute__((amdgpu_waves_per_eu(mv_waves<T>())))
 
@@ -1665,7 +1671,7 @@ __global__ __launch_bounds__(NTHREADS) GID_MV_ATTR(KB) void kb_pcg1(const BatchA
     pcg_body<KB, true>(ba.a[c], clip_grid(ba.wg_pix, c), st, smem);
 }
 GID_PIXEL_KERNELS(apply_bsum, GID_NO_ATTR, wg_bs)
-GID_PIXEL_KERNELS(energy, GID_NO_ATTR, wg_pix)
+GID_PIXEL_KERNELS(energy, GID_W3_ATTR, wg_pix)
 GID_PIXEL_KERNELS(output, GID_NO_ATTR, wg_pix)
 
 __global__ __launch_bounds__(NTHREADS) void k_scan(Args a, Step st) {
