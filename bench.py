@@ -281,7 +281,9 @@ def bench_video(args, clip, workload, learned=True):
     # matched candidate is timed in full, and the same schedule from the plain
     # start (no network) is its control
     cands = []
-    for Pl in sorted({w["P"], 7, 6, 5}, reverse=True):
+    pcands = sorted({int(v) for v in args.learned_pcg.split(",")} if args.learned_pcg else {w["P"], 7, 6, 5},
+                    reverse=True)
+    for Pl in pcands:
         t, d = run(Pl, True, 2, 1)
         cands.append((t, d))
         log(f"learned, {Pl} PCG per outer iteration: {d}")
@@ -383,6 +385,9 @@ def main() -> int:
     ap.add_argument("--frames", type=int, default=None, help="frames per clip (default: the workload's)")
     ap.add_argument("--learned", choices=("on", "off"), default="on")
     ap.add_argument("--train-frames", type=int, default=3000, help="training pairs for the learned warm start")
+    ap.add_argument("--learned-pcg", default="",
+                    help="PCG iterations per outer iteration tried with the learned start, comma-separated "
+                         "(default: the workload's, 7, 6, 5)")
     ap.add_argument("--extras", choices=("on", "off", "batch"), default="on",
                     help="also the 640x480 and 1280x720 plain lines and the 16-clip batch (batch: the batch only)")
     ap.add_argument("--cpu", choices=("on", "off"), default="on", help="time the FP64 oracle on the host")

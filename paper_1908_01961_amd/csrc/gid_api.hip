@@ -74,8 +74,15 @@ struct gid_ctx {
     int target_first = 1;          // first outer iteration whose energy is checked (1-based)
     int pend_first = 1;
     double* h_target = nullptr;    // pinned slot the target is uploaded from
-    // replayable schedules keyed by (refine, temporal, record, energy target)
-    hipGraphExec_t graphs[16] = {};
+    // energy-target mode: the outer iterations after the first check are
+    // enqueued by gid_synchronize, only when the frame has not met its target
+    bool pend_rest = false;
+    bool pend_refine = false;
+    Args pend_args{};
+    float* pend_layers = nullptr;
+    // replayable schedules keyed by (refine, temporal, record, energy target,
+    // iterations after the first check)
+    hipGraphExec_t graphs[32] = {};
     hipStream_t cap_stream = nullptr;
     // kernel timing
     bool profiling = false;
@@ -299,14 +306,15 @@ bool colours_valid(const double* b, int nk) {
 // With check (energy-target mode) the energy is evaluated after every outer
 // iteration into slot g and compared with the frame's target on the device.
 // Checks start after outer iteration first (1-based; the last iteration is
-// always checked).
+// always checked).  Outer iterations g0 .. g1 - 1 of the G are enqueued.
 template <typename LaunchFn>
 hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& launch, int* nslots,
-                            bool check = false, int first = 1) {
+                            bool check = false, int first = 1, int g0 = 0, int g1 = -1) {
     int slot = 0;
     hipError_t e = hipSuccess;
     if (check) record = false;
-    for (int g = 0; g < G; ++g) {
+    if (g1 < 0) g1 = G;
+    for (int g = g0; g < g1; ++g) {
         Step s{};
         s.gn = g;
         if ((e = launch(KN_GN_BUILD, s)) != hipSuccess) return e;
@@ -353,11 +361,18 @@ hipError_t enqueue_schedule(int G, int P, bool refine, bool record, LaunchFn&& l
     return hipSuccess;
 }
 
-hipError_t enqueue_outer(gid_ctx* c, hipStream_t st, const Args& base, bool refine, bool record, int* nslots) {
+// Outer iterations of the frame's schedule: all of them (part 0), or in energy-
+// target mode those through the first check (part 1) and those after it (part 2).
+int target_split(const gid_ctx* c) { return std::min(std::max(c->target_first, 1), c->target_gn); }
+
+hipError_t enqueue_outer(gid_ctx* c, hipStream_t st, const Args& base, bool refine, bool record, int* nslots,
+                         int part = 0) {
     const bool check = c->target > 0.0;
-    return enqueue_schedule(check ? c->target_gn : c->prm.gn_iters, c->prm.pcg_iters, refine, record,
+    const int G = check ? c->target_gn : c->prm.gn_iters;
+    const int g0 = part == 2 ? target_split(c) : 0, g1 = part == 1 ? target_split(c) : G;
+    return enqueue_schedule(G, c->prm.pcg_iters, refine, record,
                             [&](Kern k, const Step& s) { return L1(c, st, k, base, s); }, nslots, check,
-                            c->target_first);
+                            c->target_first, g0, g1);
 }
 
 // Capture a schedule into a graph on a private stream (the caller's may be the
@@ -379,16 +394,17 @@ hipError_t capture_graph(hipStream_t* cap, EnqueueFn&& enqueue, hipGraphExec_t* 
     return e;
 }
 
-gid_status run_outer(gid_ctx* c, const Args& base, bool refine, bool record, int* nslots) {
+gid_status run_outer(gid_ctx* c, const Args& base, bool refine, bool record, int* nslots, int part = 0) {
     if (!c->prm.use_graph || c->profiling) {
-        GID_HIP(c, enqueue_outer(c, c->stream, base, refine, record, nslots));
+        GID_HIP(c, enqueue_outer(c, c->stream, base, refine, record, nslots, part));
         return GID_OK;
     }
-    const int key = (refine ? 1 : 0) | (base.temporal ? 2 : 0) | (record ? 4 : 0) | (c->target > 0.0 ? 8 : 0);
+    const int key = (refine ? 1 : 0) | (base.temporal ? 2 : 0) | (record ? 4 : 0) | (c->target > 0.0 ? 8 : 0) |
+                    (part == 2 ? 16 : 0);
     if (!c->graphs[key]) {
         hipGraphExec_t ex = nullptr;
         hipError_t e = capture_graph(&c->cap_stream, [&](hipStream_t cs) {
-            return enqueue_outer(c, cs, base, refine, record, nslots);
+            return enqueue_outer(c, cs, base, refine, record, nslots, part);
         }, &ex);
         if (e != hipSuccess) return fail(c, GID_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
         c->graphs[key] = ex;
@@ -697,11 +713,22 @@ gid_status gid_decompose_frame(gid_ctx* c, const float* frame, const uint8_t* id
     const bool refine = mode == GID_REFINE_EVERY_STEP || (mode == GID_REFINE_FIRST_FRAME && c->frame_index == 0);
     const bool record = c->prm.record_energy != 0;
     int nslots = 0;
-    if ((s = run_outer(c, a, refine, record, &nslots)) != GID_OK) return s;
-    Args o = a;
-    o.out = layers;
-    GID_HIP(c, L1(c, c->stream, KN_OUTPUT, o, Step{}));
+    // energy-target mode: the iterations through the first check now; the rest,
+    // and the output pass, from gid_synchronize once the device flags are back
+    // (a frame that met its target skips them instead of replaying them as
+    // launches that return at once)
+    const bool split = c->target > 0.0 && target_split(c) < c->target_gn;
+    if ((s = run_outer(c, a, refine, record, &nslots, split ? 1 : 0)) != GID_OK) return s;
+    if (!split) {
+        Args o = a;
+        o.out = layers;
+        GID_HIP(c, L1(c, c->stream, KN_OUTPUT, o, Step{}));
+    }
     GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSTATS, hipMemcpyDeviceToHost, c->stream));
+    c->pend_rest = split;
+    c->pend_refine = refine;
+    c->pend_args = a;
+    c->pend_layers = layers;
     c->pending = true;
     c->pend_b = b_out;
     c->pend_stats = stats;
@@ -725,8 +752,8 @@ gid_status gid_set_energy_target(gid_ctx* c, double target, int32_t max_gn) {
     if (c->pending) return fail(c, GID_ERR_STATE, "the previous frame is pending: call gid_synchronize first");
     const int gn = target > 0.0 ? max_gn : 0;
     if (gn != c->target_gn) {   // the target-mode schedule is captured for one iteration count
-        for (int k = 8; k < 16; ++k)
-            if (c->graphs[k]) {
+        for (int k = 8; k < 32; ++k)
+            if ((k & 8) && c->graphs[k]) {
                 (void)hipGraphExecDestroy(c->graphs[k]);
                 c->graphs[k] = nullptr;
             }
@@ -741,8 +768,8 @@ gid_status gid_set_energy_check_from(gid_ctx* c, int32_t first_gn) {
     if (first_gn < 1 || first_gn > 64) return fail(c, GID_ERR_INVALID_ARG, "first_gn must be in 1..64");
     if (c->pending) return fail(c, GID_ERR_STATE, "the previous frame is pending: call gid_synchronize first");
     if (first_gn != c->target_first) {   // the target-mode schedule is captured for one first check
-        for (int k = 8; k < 16; ++k)
-            if (c->graphs[k]) {
+        for (int k = 8; k < 32; ++k)
+            if ((k & 8) && c->graphs[k]) {
                 (void)hipGraphExecDestroy(c->graphs[k]);
                 c->graphs[k] = nullptr;
             }
@@ -754,6 +781,24 @@ gid_status gid_set_energy_check_from(gid_ctx* c, int32_t first_gn) {
 gid_status gid_synchronize(gid_ctx* c) {
     if (!c) return GID_ERR_INVALID_ARG;
     GID_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->pending && c->pend_rest) {
+        // the flags after the first energy check: the frame's remaining outer
+        // iterations only while it has not met its target (nor was rejected)
+        c->pend_rest = false;
+        if (c->h_scal[S_BADIN] == 0.0 && c->h_scal[S_DONE] == 0.0) {
+            int ns = 0;
+            const gid_status s = run_outer(c, c->pend_args, c->pend_refine, false, &ns, 2);
+            if (s != GID_OK) {
+                c->pending = false;
+                return s;
+            }
+        }
+        Args o = c->pend_args;
+        o.out = c->pend_layers;
+        GID_HIP(c, L1(c, c->stream, KN_OUTPUT, o, Step{}));
+        GID_HIP(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double) * NSTATS, hipMemcpyDeviceToHost, c->stream));
+        GID_HIP(c, hipStreamSynchronize(c->stream));
+    }
     if (c->ev_used) GID_HIP(c, collect_times(c));
     if (!c->pending) return GID_OK;
     c->pending = false;
