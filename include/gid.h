@@ -153,16 +153,22 @@ gid_status gid_reset_clip(gid_ctx *ctx);
 gid_status gid_decompose_frame(gid_ctx *ctx, const float *frame_dev, const uint8_t *cluster_ids_dev,
                                float *layers_dev, double *base_colors_host, gid_frame_stats *stats);
 
-/* Wait for the context's stream; completes pending host outputs.  Returns
- * GID_ERR_NUMERIC if the last frame's final energy is not finite. */
+/* Wait for the context's stream; completes pending host outputs.  In
+ * energy-target mode (gid_set_energy_target) with checks starting before the
+ * last outer iteration, a pending frame's iterations after its first check and
+ * its output pass are enqueued here, on the context's stream, once the device's
+ * flags show the frame has not met its target; a frame that has met it goes
+ * straight to its output pass.  Returns GID_ERR_NUMERIC if the last frame's
+ * final energy is not finite. */
 gid_status gid_synchronize(gid_ctx *ctx);
 
 /* Energy-target continuation (used by the learned warm start's matched-energy
  * runs; not part of the paper's fixed schedule of Sec. 7.1).  With target > 0
  * every following frame runs up to max_gn (1..64) outer iterations instead of
  * params.gn_iters and evaluates E of Sec. 6 after each one; once E <= target the
- * frame's remaining iterations are skipped on the device, with no host round
- * trip.  gid_frame_stats.gn_done then reports the iterations run and
+ * frame's remaining iterations are skipped: those after the first check are not
+ * enqueued at all (gid_synchronize decides from the device's flags), later ones
+ * return on the device.  gid_frame_stats.gn_done then reports the iterations run and
  * energy_half their energies (n_half = gn_done); energy_final is the energy after
  * the last iteration run.  Call it between frames: target applies to every
  * following frame until changed; target <= 0 restores the fixed schedule.
