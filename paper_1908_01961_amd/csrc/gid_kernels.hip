@@ -72,10 +72,20 @@ __device__ __forceinline__ TileSet tiles_of(const Args& a, const Lc& lc) {
     return s;
 }
 
-// Tile coordinates of tile l.
+// Tile coordinates of tile l: the tiles are numbered in vertical strips of 4
+// tile columns (the last strip holds the ntx % 4 columns left over), each strip
+// row by row, so that the tiles an XCD has in flight (a contiguous range of
+// numbers) form a compact block and a tile's upper neighbour was started a few
+// tiles before it.  At 1920x1080 K = 10 (same box, same run) the PCG iteration
+// takes 258.3 us against 261.0 us in row-major order; strips of 2 took 276 us,
+// of 8 264.5 us, and folding the leftover columns into a wider last strip 263.0 us.
+constexpr int TSTRIP = 4;
 __device__ __forceinline__ void tile_xy(const Args& a, const TileSet& s, int l, int& tx, int& ty) {
-    tx = l % a.ntx;
-    ty = l / a.ntx;
+    const int full = a.nty * TSTRIP, st = l / full, x0 = st * TSTRIP;
+    const int ws = a.ntx - x0 < TSTRIP ? a.ntx - x0 : TSTRIP;
+    const int rem = l - st * full;
+    ty = rem / ws;
+    tx = x0 + rem - ty * ws;
 }
 
 __device__ __forceinline__ Lc whole_grid() { return Lc{xcd_order((int)blockIdx.x, (int)gridDim.x), (int)gridDim.x}; }
