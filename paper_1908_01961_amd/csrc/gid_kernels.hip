@@ -72,15 +72,23 @@ __device__ __forceinline__ TileSet tiles_of(const Args& a, const Lc& lc) {
     return s;
 }
 
-// Tile coordinates of tile l: the tiles are numbered in vertical strips of 4
-// tile columns (the last strip holds the ntx % 4 columns left over), each strip
-// row by row, so that the tiles an XCD has in flight (a contiguous range of
-// numbers) form a compact block and a tile's upper neighbour was started a few
-// tiles before it.  At 1920x1080 K = 10 (same box, same run) the PCG iteration
-// takes 258.3 us against 261.0 us in row-major order; strips of 2 took 276 us,
-// of 8 264.5 us, and folding the leftover columns into a wider last strip 263.0 us.
+// Tile coordinates of tile l.  When a launch gives its workgroups 4 tiles or more
+// each (s.step is the workgroups per XCD), the tiles are numbered in vertical
+// strips of 4 tile columns (the last strip holds the ntx % 4 columns left over),
+// each strip row by row, so that the tiles an XCD has in flight (a contiguous
+// range of numbers) form a compact block and a tile's upper neighbour was started
+// a few tiles before it; otherwise row by row.  Same box, same run: at 1920x1080
+// K = 10 (10.5 tiles per workgroup) the PCG iteration takes 258.3 us in strips
+// against 261.0 us row by row (strips of 2 columns 276 us, of 8 264.5 us, a wider
+// last strip 263.0 us); at 640x480 K = 6 (1.25 tiles per workgroup) 36.8 us in
+// strips against 35.4 us row by row.
 constexpr int TSTRIP = 4;
 __device__ __forceinline__ void tile_xy(const Args& a, const TileSet& s, int l, int& tx, int& ty) {
+    if (a.ntiles < 32 * s.step) {
+        tx = l % a.ntx;
+        ty = l / a.ntx;
+        return;
+    }
     const int full = a.nty * TSTRIP, st = l / full, x0 = st * TSTRIP;
     const int ws = a.ntx - x0 < TSTRIP ? a.ntx - x0 : TSTRIP;
     const int rem = l - st * full;
